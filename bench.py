@@ -1,0 +1,191 @@
+"""Throughput of the full GPE + Cahn-Hilliard time step on one MI355X.
+
+Workload: 3-D rising bubble on a 256^3 grid with no-slip walls (density and
+viscosity ratio 10, Eotvos 10, Morton 1e-4, W = 2, M = 0.02, D3Q15 CH
+stencils), FP32.  One step = three TVD-RK3 flow stages + four RK4 CH stages.
+The state is initialised in HBM before the timed region; the timed region is
+K graph-replayed steps between two synchronisations.
+
+Prints one JSON line: MLUPS (cells x steps / s / 1e6), the roofline of the
+dominant kernel (algorithmic bytes per launch / mean launch time from HIP
+events on the solver's stream, against the 8 TB/s HBM peak), the step-level
+roofline, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS per full RK3 step (3D 256^3) vs HBM roofline; learned-coarse speedup"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def csrc_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2011_00814_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def problem(n: int, precision: str):
+    from paper_2011_00814_amd import workloads as W
+
+    prob, _ = W.rising_bubble_3d(nx=4, ny=4, nz=4, precision=precision)  # parameters only
+    prob = dict(prob, n=(n, n, n))
+    prob["init"] = {"kind": 2, "center": (n / 2, n / 2, 48.0), "radius": 16.0, "width": prob["width"]}
+    return prob
+
+
+def measured_traffic(kernel: str, precision: str):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters, valid only while the kernel sources are unchanged."""
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    ent = data.get(f"{kernel}:{precision}")
+    if not ent or ent.get("csrc_hash") != csrc_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(n: int, precision: str, z_sample: int = 64, steps: int = 1):
+    import ctypes
+
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2011_00814_amd import workloads as W
+
+    prob, st = W.rising_bubble_3d(nx=n, ny=n, nz=z_sample, zc=48.0, precision="fp64")
+    try:
+        threads = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
+    except OSError:
+        threads = 1
+    t0 = time.perf_counter()
+    O.run(prob, st, steps)
+    dt = time.perf_counter() - t0
+    cells = n * n * z_sample
+    return {
+        "value": cells * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{steps} step(s) of the same 3-D bubble physics on a {n}x{n}x{z_sample} slab "
+                  f"(bottom of the 256^3 domain, bubble included), FP64 C oracle, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2011_00814_amd import gpe
+
+    gpe.lib()  # fails loudly if the HIP library is not built
+    prob = problem(args.n, args.precision)
+    s = gpe.Solver(prob, None, device="cuda:0")
+    ncell = args.n ** 3
+    d0 = s.diagnostics()
+
+    # per-kernel launch times (HIP events on the solver's stream)
+    ktimes = s.kernel_times(args.kernel_steps)
+    s.run(args.warmup)
+    s.synchronize()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(s.stream)
+    s.run(args.steps)
+    stop.record(s.stream)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    d = s.diagnostics()
+    s.close()
+    ms_per_step = ms_total / args.steps
+    mlups = ncell * args.steps / (ms_total / 1e3) / 1e6
+
+    esize = 4 if args.precision == "fp32" else 8
+    dom = max(ktimes, key=lambda r: r[1])
+    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
+    traffic = measured_traffic(dom[0], args.precision)
+    step_bytes = sum(r[2] for r in ktimes)
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D rising bubble {args.n}^3, no-slip walls, density/viscosity ratio 10, "
+                        "Eo 10, Mo 1e-4, W 2, M 0.02, D3Q15 CH stencils, RK3 flow + RK4 CH",
+            "grid": [args.n] * 3,
+            "precision": args.precision,
+            "wall_s": round(wall, 3),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom[0],
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": dom[2],
+            "launch_ms": round(dom[1], 5),
+        },
+        "step_roofline": {
+            "algorithmic_bytes_per_step": step_bytes,
+            "bytes_per_cell_step": step_bytes / ncell,
+            "achieved": round(step_gbs, 1),
+            "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+            "roofline_mlups": round(HBM_PEAK_GBS * 1e9 / (step_bytes / ncell) / 1e6, 1),
+        },
+        "kernels": [{"name": r[0], "ms": round(r[1], 5), "bytes": r[2],
+                     "gbs": round(r[2] / (r[1] * 1e-3) / 1e9, 1)} for r in ktimes],
+        "diag": {"finite": d["finite"], "steps_run": d["step"],
+                 "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass_abs0"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.n, args.precision)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * gpe.h -- C-ABI of libgpe, an MI355X (gfx950) implementation of the fully
+ * explicit time step of the general-pressure-equation (GPE) + Cahn-Hilliard
+ * two-phase solver of J.-J. Huang, "Numerical simulation of two-phase
+ * incompressible viscous flows using general pressure equation"
+ * (arXiv 2011.00814).
+ *
+ * One time step (Sec. 3) = three TVD-RK3 stages of the pressure equation and
+ * the momentum equations on a staggered grid with the phase field frozen,
+ * the space-time averaged cell-centre velocity, then the Cahn-Hilliard
+ * sub-step (TVD-RK2 in 2-D and axisymmetric geometry, classic RK4 in 3-D).
+ *
+ * Conventions shared by every call:
+ *  - Lattice units: grid spacing dx = 1.  dt and cs2 are free parameters
+ *    (the paper fixes cs = dx / (sqrt(3) dt), Sec. 2, general pressure eq.).
+ *  - Layout: every field is a dense array of shape (nz, ny, nx), x fastest
+ *    (nz = 1 in 2-D).  Velocity components are stored on the LOW face of
+ *    their cell: u[k][j][i] sits between cells i-1 and i (Sec. 3, index
+ *    convention of the divergence stencil).  For walls and symmetry planes
+ *    the boundary-normal face of cell 0 is on the boundary and is always 0.
+ *  - Axisymmetric geometry (Sec. 2, axisymmetric equations): x is the axial
+ *    coordinate z, y the radial coordinate r (cell centres r = j + 1/2),
+ *    u = u_z, v = u_r; the y-low boundary is the axis (GPE_BC_SYMMETRY).
+ *  - Ownership: the caller owns all device memory (one workspace buffer)
+ *    and the HIP stream.  The library never allocates or frees device
+ *    memory; gpe_destroy frees host metadata only.
+ *  - Errors: every int-returning call returns GPE_OK (0) or a negative
+ *    gpe_error code; no exception crosses the ABI.  gpe_strerror names them.
+ *  - Threading: one handle per stream; a handle is not thread-safe.
+ *  - Precision: GPE_FP64 (reference) or GPE_FP32 (fast).  Reductions of
+ *    gpe_diagnostics accumulate in FP64 in both modes.
+ */
+#ifndef GPE_H
+#define GPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum gpe_error {
+  GPE_OK = 0,
+  GPE_EINVAL = -1,       /* invalid argument or parameter set              */
+  GPE_EUNSTABLE = -2,    /* a linear stability estimate is exceeded         */
+  GPE_EWORKSPACE = -3,   /* workspace too small or misaligned               */
+  GPE_EHIP = -4,         /* a HIP runtime call failed                       */
+  GPE_ENONFINITE = -5    /* the state holds NaN / Inf (sticky per handle)   */
+};
+
+enum gpe_geometry { GPE_GEOM_2D = 0, GPE_GEOM_AXISYM = 1, GPE_GEOM_3D = 2 };
+enum gpe_precision { GPE_FP64 = 0, GPE_FP32 = 1 };
+enum gpe_bc { GPE_BC_PERIODIC = 0, GPE_BC_WALL = 1, GPE_BC_SYMMETRY = 2 };
+/* isotropic lattice of the CH derivatives (Sec. 3, isotropic schemes) */
+enum gpe_lattice { GPE_D2Q9 = 9, GPE_D3Q15 = 15, GPE_D3Q19 = 19, GPE_D3Q27 = 27 };
+enum gpe_field { GPE_FIELD_P = 0, GPE_FIELD_U = 1, GPE_FIELD_V = 2, GPE_FIELD_W = 3,
+                 GPE_FIELD_PHI = 4 };
+enum gpe_copy_dir { GPE_H2D = 0, GPE_D2H = 1 };
+/* in-kernel initial phase field, used when gpe_init_state gets h_phi0 = NULL */
+enum gpe_init_kind {
+  GPE_INIT_NONE = 0,     /* phi = init_amp everywhere                                  */
+  GPE_INIT_DROP = 1,     /* phi = tanh(2 (R - r) / init_width): liquid sphere/disc     */
+  GPE_INIT_BUBBLE = 2,   /* phi = tanh(2 (r - R) / init_width): gas sphere/disc        */
+  GPE_INIT_LAYER = 3     /* phi = tanh(2 (y - y0(x)) / init_width) (2-D) or in z (3-D),
+                            y0 = init_center[1 or 2] + init_amp cos(2 pi x_c / nx)     */
+};
+
+/* Physical and numerical parameters in lattice units (dx = 1). */
+typedef struct gpe_params {
+  int32_t geometry;        /* gpe_geometry                                             */
+  int32_t precision;       /* gpe_precision                                            */
+  int32_t n[3];            /* cells along x, y, z; n[2] = 1 unless 3-D; each >= 3      */
+  int32_t bc[6];           /* gpe_bc of x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; an axis is
+                              periodic on both sides or on neither                      */
+  int32_t lattice;         /* GPE_D2Q9 in 2-D/axisym; GPE_D3Q15/19/27 in 3-D           */
+  int32_t allow_unstable;  /* 1: skip the GPE_EUNSTABLE check of gpe_init_state        */
+  int32_t reserved0;       /* must be 0                                                */
+  double dt;               /* time step                                                */
+  double cs2;              /* c_s^2 of the pressure equation                          */
+  double rho_l, rho_g;     /* densities of liquid (phi = +1) and gas (phi = -1)       */
+  double eta_l, eta_g;     /* dynamic viscosities (bulk viscosity eta_b = eta)         */
+  double sigma;            /* surface tension of the force -sigma phi grad(mu)        */
+  double mobility;         /* Cahn-Hilliard mobility M                                */
+  double width;            /* interface width W: a = 3/(4W), kappa = 3W/8              */
+  double g[3];             /* body force; buoyancy (rho(phi) - rho_ref) g              */
+  double rho_ref;          /* reference density absorbed into the pressure            */
+  int32_t init_kind;       /* gpe_init_kind (only when h_phi0 == NULL)                 */
+  int32_t reserved;
+  double init_center[3];   /* cell-centre coordinates (x_c = i + 1/2)                  */
+  double init_radius;
+  double init_width;       /* profile width (usually = width)                          */
+  double init_amp;
+} gpe_params;
+
+/* The paper's problem statement (Sec. 4 set-up): characteristic length L_c
+ * resolved by N_L cells, characteristic time T_c = L_c / U_c resolved by N_t
+ * steps, so that dx = dt = 1, U_c = N_L / N_t and c_s^2 = 1/3. */
+typedef struct gpe_problem {
+  int32_t geometry, precision;
+  int32_t n[3];
+  int32_t bc[6];
+  int32_t lattice;
+  int32_t capillary_scale; /* 1: U_c = sigma / eta_L (flows with surface tension)     */
+  int32_t reserved0;       /* must be 0                                                */
+  double N_L;              /* cells per characteristic length L_c                     */
+  double N_t;              /* steps per characteristic time T_c                       */
+  double r_rho;            /* rho_L / rho_G (rho_L = 1)                                */
+  double r_eta;            /* eta_L / eta_G                                            */
+  double Re;               /* rho_L U_c L_c / eta_L                                    */
+  double We;               /* rho_L U_c^2 L_c / sigma (0: no surface tension); ignored
+                              when capillary_scale = 1 (sigma = U_c eta_L)             */
+  double Pe;               /* U_c L_c^2 / (M sigma_ref), sigma_ref = 1                 */
+  double Cn;               /* W / L_c                                                  */
+  double G[3];             /* body force in units of U_c^2 / L_c                      */
+  int32_t rho_ref_kind;    /* 0: rho_ref = 0, 1: rho_L, 2: rho_G                      */
+  int32_t reserved;
+} gpe_problem;
+
+/* Diagnostics (FP64 reductions in a fixed order: bitwise reproducible). */
+typedef struct gpe_diag {
+  int64_t step;            /* completed time steps                                     */
+  double t;                /* step * dt (or the value set by gpe_set_step_time)        */
+  double mass;             /* sum phi (sum r_j phi in axisymmetric geometry)           */
+  double mass_abs0;        /* sum |phi| (r-weighted) of the initial state: normaliser  */
+  double ke;               /* 1/2 sum over faces of rho_f u_f^2 (r-weighted if axisym) */
+  double max_div;          /* max |div u| over cells                                   */
+  double phi_min, phi_max;
+  double umax;             /* max |u_f| over all face components                       */
+  int32_t finite;          /* 1 if p, u, v, w, phi are all finite                      */
+  int32_t reserved;
+} gpe_diag;
+
+typedef struct gpe_state gpe_state;
+
+/* Map the problem statement (Sec. 4 parameter choices: dx = L_c/N_L,
+ * dt = T_c/N_t, rho_L = 1, U_c = sigma/eta_L when capillary_scale, W = Cn L_c,
+ * M from Pe) to lattice-unit parameters.  init_* fields of *out are zeroed.
+ * Returns GPE_OK or GPE_EINVAL. */
+int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out);
+
+/* Bytes of the caller-owned device workspace needed for *p: every resident
+ * field (state, two RK stage sets, phase-field stage buffers, face velocity
+ * sums) plus reduction scratch, each 256-byte aligned.  0 if *p is invalid. */
+size_t gpe_workspace_bytes(const gpe_params* p);
+
+/* Validate *p, lay the fields out in d_workspace (device pointer, >= bytes
+ * from gpe_workspace_bytes, 256-byte aligned) and set the initial state on
+ * hip_stream (a hipStream_t; NULL = the null stream): u = v = w = 0,
+ * p = h_p0 or 0, phi = h_phi0 or the in-kernel profile of p->init_kind.
+ * h_phi0 / h_p0 are host arrays of n[0]*n[1]*n[2] doubles or NULL.
+ * Returns GPE_EUNSTABLE when an estimate of the linear stability limits of
+ * the acoustic, viscous, pressure-diffusion or CH parts is exceeded and
+ * p->allow_unstable == 0.  On success *out receives a new handle. */
+int gpe_init_state(const gpe_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+                   const double* h_phi0, const double* h_p0, gpe_state** out);
+
+/* One full time step (Sec. 3): three flow TVD-RK3 stages with phi frozen,
+ * the space-time averaged centre velocity, the CH sub-step.  Asynchronous. */
+int gpe_rk3_step(gpe_state* s);
+
+/* n time steps, replayed from a captured HIP graph of one step when the
+ * stream is not the null stream.  Asynchronous.  n >= 0. */
+int gpe_run_n(gpe_state* s, int64_t n);
+
+/* Reduce the current state into *out (synchronises the stream).  Sets the
+ * sticky GPE_ENONFINITE on the handle and returns it if the state is not
+ * finite; *out is filled either way. */
+int gpe_diagnostics(gpe_state* s, gpe_diag* out);
+
+/* Copy one field between the device state and a host array of
+ * n[0]*n[1]*n[2] doubles (converted from/to the state precision), in the
+ * layout above.  GPE_FIELD_W is valid in 3-D only; for walls and symmetry
+ * planes the boundary-normal faces written by GPE_H2D must be 0.
+ * bytes must equal n[0]*n[1]*n[2]*8.  Synchronous. */
+int gpe_copy_field(gpe_state* s, int field, int dir, void* host, size_t bytes);
+
+/* Byte offset of a state field inside the workspace (elements of the state
+ * precision, layout above), or (size_t)-1 for an invalid field. */
+size_t gpe_field_offset(const gpe_state* s, int field);
+
+/* Overwrite the step counter and time (checkpoint restart). */
+int gpe_set_step_time(gpe_state* s, int64_t step, double t);
+
+/* Average device duration of every kernel of the step, measured with HIP
+ * events around each launch over nsteps eager steps on the handle's stream
+ * (the state advances by nsteps).  names[i] receives a static string,
+ * ms[i] the mean duration in milliseconds, bytes[i] the algorithmic HBM
+ * bytes of one launch (each field read once and written once).  Returns
+ * the number of kernels (<= max) or a negative gpe_error. */
+int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names,
+                     double* ms, double* bytes);
+
+/* Free the host-side handle (never the workspace). NULL is ignored. */
+void gpe_destroy(gpe_state* s);
+
+const char* gpe_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPE_H */

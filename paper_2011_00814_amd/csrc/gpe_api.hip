@@ -1,0 +1,611 @@
+// gpe_api.cpp -- host side of libgpe: parameter validation and stability
+// estimates, workspace layout, the per-step launch sequence, HIP-graph
+// replay, diagnostics and field transfer.  Implements include/gpe.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gpe.h"
+#include "gpe_device.hpp"
+#include "gpe_misc.hpp"
+
+namespace {
+
+using gpe::ChArgs;
+using gpe::Consts;
+using gpe::FlowArgs;
+using gpe::Grid;
+
+// Workspace buffers (internal axis order for velocities: X, Y, Z).
+enum Buf {
+  B_Q0 = 0,   // p, uX, uY, uZ at time level n        (4 slots)
+  B_Q1 = 4,   // first RK stage                       (4 slots)
+  B_Q2 = 8,   // second RK stage                      (4 slots)
+  B_PHI = 12, // phi*
+  B_PHA = 13, // CH stage buffer A
+  B_PHB = 14, // CH stage buffer B (RK4)
+  B_ACC = 15, // RK4 running sum
+  B_US = 16,  // u^n + u^{n+1} on X, Y, Z faces      (3 slots)
+  B_SCR = 19, // reduction scratch
+  B_COUNT = 20
+};
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct gpe_state {
+  gpe_params P;
+  int dim;                 // 2 or 3
+  bool axi;
+  size_t esize;            // bytes per element
+  size_t ncell;
+  Grid grid;               // internal
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  size_t off[B_COUNT];     // byte offsets; SIZE_MAX when absent
+  int64_t step;
+  double t;
+  double mass_abs0;
+  int sticky;
+  hipGraphExec_t graph;
+  bool graph_ok;
+};
+
+namespace {
+
+bool has_buf(const gpe_state* s, int b) { return s->off[b] != (size_t)-1; }
+
+template <typename T>
+T* buf(const gpe_state* s, int b) {
+  return has_buf(s, b) ? reinterpret_cast<T*>(s->ws + s->off[b]) : nullptr;
+}
+
+int dim_of(const gpe_params* p) { return p->geometry == GPE_GEOM_3D ? 3 : 2; }
+
+// Which workspace buffers a parameter set needs.
+void needed(const gpe_params* p, bool need[B_COUNT]) {
+  const int dim = dim_of(p);
+  for (int b = 0; b < B_COUNT; ++b) need[b] = true;
+  if (dim == 2) {
+    need[B_Q0 + 2] = need[B_Q1 + 2] = need[B_Q2 + 2] = false;  // no Y velocity
+    need[B_US + 1] = false;
+    need[B_PHB] = need[B_ACC] = false;                         // RK2 only
+  }
+}
+
+size_t scratch_bytes() { return (size_t)(gpe::kDiagBlocks * 8 + 8) * sizeof(double); }
+
+int validate(const gpe_params* p) {
+  if (!p) return GPE_EINVAL;
+  if (p->geometry < 0 || p->geometry > 2) return GPE_EINVAL;
+  if (p->precision != GPE_FP64 && p->precision != GPE_FP32) return GPE_EINVAL;
+  const int dim = dim_of(p);
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      if (p->n[a] < 3) return GPE_EINVAL;
+    } else if (p->n[a] != 1) {
+      return GPE_EINVAL;
+    }
+  }
+  const double ncell = (double)p->n[0] * p->n[1] * p->n[2];
+  if (ncell > 4.0e9) return GPE_EINVAL;
+  if ((double)p->n[0] * p->n[1] > 2.0e9) return GPE_EINVAL;
+  for (int a = 0; a < dim; ++a) {
+    const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return GPE_EINVAL;
+    if ((lo == GPE_BC_PERIODIC) != (hi == GPE_BC_PERIODIC)) return GPE_EINVAL;
+  }
+  if (dim == 2 && p->lattice != GPE_D2Q9) return GPE_EINVAL;
+  if (dim == 3 && p->lattice != GPE_D3Q15 && p->lattice != GPE_D3Q19 && p->lattice != GPE_D3Q27)
+    return GPE_EINVAL;
+  if (p->geometry == GPE_GEOM_AXISYM) {
+    if (p->bc[2] != GPE_BC_SYMMETRY) return GPE_EINVAL;  // the axis
+    if (p->g[1] != 0.0) return GPE_EINVAL;               // body force along the axis only
+  }
+  if (!(p->dt > 0) || !(p->cs2 > 0)) return GPE_EINVAL;
+  if (!(p->rho_l > 0) || !(p->rho_g > 0)) return GPE_EINVAL;
+  if (!(p->eta_l >= 0) || !(p->eta_g >= 0)) return GPE_EINVAL;
+  if (!(p->sigma >= 0) || !(p->mobility >= 0) || !(p->width > 0)) return GPE_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->g[a])) return GPE_EINVAL;
+  if (!std::isfinite(p->rho_ref)) return GPE_EINVAL;
+  if (p->init_kind < 0 || p->init_kind > 3) return GPE_EINVAL;
+  return GPE_OK;
+}
+
+void lattice_weights(int lattice, double w[4]) {
+  switch (lattice) {
+    case GPE_D2Q9: w[0] = 4.0 / 9; w[1] = 1.0 / 9; w[2] = 1.0 / 36; w[3] = 0; break;
+    case GPE_D3Q15: w[0] = 2.0 / 9; w[1] = 1.0 / 9; w[2] = 0; w[3] = 1.0 / 72; break;
+    case GPE_D3Q19: w[0] = 1.0 / 3; w[1] = 1.0 / 18; w[2] = 1.0 / 36; w[3] = 0; break;
+    default: w[0] = 8.0 / 27; w[1] = 2.0 / 27; w[2] = 1.0 / 54; w[3] = 1.0 / 216; break;
+  }
+}
+
+// Largest eigenvalue of minus the isotropic Laplacian symbol,
+// 6 sum_i w_i (1 - cos(k . e_i)), scanned over the Brillouin zone.
+double iso_lap_max(int lattice, int dim) {
+  double w[4];
+  lattice_weights(lattice, w);
+  const int N = 24;
+  double best = 0;
+  for (int a = 0; a <= N; ++a)
+    for (int b = 0; b <= N; ++b)
+      for (int c = 0; c <= (dim == 3 ? N : 0); ++c) {
+        const double k[3] = {M_PI * a / N, M_PI * b / N, M_PI * c / N};
+        double s = 0;
+        for (int ez = -1; ez <= 1; ++ez) {
+          if (dim == 2 && ez != 0) continue;
+          for (int ey = -1; ey <= 1; ++ey)
+            for (int ex = -1; ex <= 1; ++ex) {
+              const int nnz = (ex != 0) + (ey != 0) + (ez != 0);
+              if (nnz == 0) continue;
+              s += w[nnz] * (1 - std::cos(k[0] * ex + k[1] * ey + k[2] * ez));
+            }
+        }
+        best = std::fmax(best, 6 * s);
+      }
+  return best;
+}
+
+// Linear stability estimates (returns the largest ratio to its limit).
+double stability_ratio(const gpe_params* p) {
+  const int d = dim_of(p);
+  const double cs = std::sqrt(p->cs2);
+  // acoustic: |lambda dt| = 2 c_s dt with the averaged pressure gradient;
+  // TVD-RK3 is stable on the imaginary axis up to sqrt(3)
+  double r = 2.0 * cs * p->dt / std::sqrt(3.0);
+  const double nu_max = std::fmax(p->eta_l / p->rho_l, p->eta_g / p->rho_g);
+  // compressive viscous mode 3 nu |k|^2 <= 3 nu 4 d; RK3 real-axis limit 2.5127
+  r = std::fmax(r, 3.0 * nu_max * p->dt * 4.0 * d / 2.5127);
+  // CH linearised about phi = +-1: M lam (8a + kappa lam), RK2 limit 2, RK4 2.785
+  const double a = 3.0 / (4.0 * p->width), kappa = 3.0 * p->width / 8.0;
+  const double lam = iso_lap_max(p->lattice, d);
+  const double ch = p->mobility * p->dt * lam * (8.0 * a + kappa * lam);
+  r = std::fmax(r, ch / (d == 3 ? 2.785 : 2.0));
+  return r;
+}
+
+template <typename T>
+Consts<T> make_consts(const gpe_params* p, int dim) {
+  Consts<T> c;
+  double w[4];
+  lattice_weights(p->lattice, w);
+  c.dt = T(p->dt);
+  c.cs2 = T(p->cs2);
+  c.rho_l = T(p->rho_l);
+  c.rho_g = T(p->rho_g);
+  c.eta_l = T(p->eta_l);
+  c.eta_g = T(p->eta_g);
+  c.sigma = T(p->sigma);
+  c.mob = T(p->mobility);
+  c.a4 = T(4.0 * 3.0 / (4.0 * p->width));
+  c.kappa6 = T(6.0 * 3.0 * p->width / 8.0);
+  c.rho_ref = T(p->rho_ref);
+  if (dim == 3) {
+    c.g[0] = T(p->g[0]); c.g[1] = T(p->g[1]); c.g[2] = T(p->g[2]);
+  } else {
+    c.g[0] = T(p->g[0]); c.g[1] = T(0); c.g[2] = T(p->g[1]);
+  }
+  c.w1 = T(w[1]);
+  c.w2 = T(w[2]);
+  c.w3 = T(w[3]);
+  return c;
+}
+
+// ---- kernel sequence of one time step ----------------------------------
+struct KernelTimer {
+  bool on = false;
+  hipEvent_t ev[2 * 16];
+  int n = 0;
+};
+
+template <typename T>
+hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
+  const int geom = s->P.geometry;
+  const Consts<T> c = make_consts<T>(&s->P, s->dim);
+  hipError_t e = hipSuccess;
+  auto mark = [&]() {
+    if (kt && kt->on) (void)hipEventRecord(kt->ev[kt->n++], s->stream);
+  };
+  FlowArgs<T> f;
+  f.g = s->grid;
+  f.g.zchunk = (s->dim == 3) ? gpe::FlowTile<3>::ZC : gpe::FlowTile<2>::ZC;
+  f.c = c;
+  f.phi = buf<T>(s, B_PHI);
+  for (int a = 0; a < 3; ++a) f.usum[a] = buf<T>(s, B_US + a);
+  for (int st = 1; st <= 3; ++st) {
+    const int src = st == 1 ? B_Q0 : (st == 2 ? B_Q1 : B_Q2);
+    const int dst = st == 1 ? B_Q1 : (st == 2 ? B_Q2 : B_Q0);
+    for (int q = 0; q < 4; ++q) {
+      f.src[q] = buf<T>(s, src + q);
+      f.qn[q] = buf<T>(s, B_Q0 + q);
+      f.dst[q] = buf<T>(s, dst + q);
+    }
+    mark();
+    e = gpe::launch_flow<T>(f, geom, st, s->stream);
+    mark();
+    if (e != hipSuccess) return e;
+  }
+  ChArgs<T> h;
+  h.g = s->grid;
+  h.g.zchunk = (s->dim == 3) ? gpe::ChTile<3>::ZC : gpe::ChTile<2>::ZC;
+  h.c = c;
+  for (int a = 0; a < 3; ++a) h.usum[a] = buf<T>(s, B_US + a);
+  T* phi = buf<T>(s, B_PHI);
+  T* pa = buf<T>(s, B_PHA);
+  T* pb = buf<T>(s, B_PHB);
+  T* acc = buf<T>(s, B_ACC);
+  struct Stg { int stage; T* in; T* out; };
+  std::vector<Stg> seq;
+  if (s->dim == 2) {
+    seq = {{gpe::CH_RK2_1, phi, pa}, {gpe::CH_RK2_2, pa, phi}};
+  } else {
+    seq = {{gpe::CH_RK4_1, phi, pa}, {gpe::CH_RK4_2, pa, pb}, {gpe::CH_RK4_3, pb, pa},
+           {gpe::CH_RK4_4, pa, phi}};
+  }
+  for (const Stg& st : seq) {
+    h.phi_in = st.in;
+    h.out = st.out;
+    h.phis = phi;
+    h.acc = acc;
+    mark();
+    e = gpe::launch_ch<T>(h, geom, st.stage, s->stream);
+    mark();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_step(gpe_state* s, KernelTimer* kt = nullptr) {
+  return s->P.precision == GPE_FP64 ? enqueue_step_t<double>(s, kt) : enqueue_step_t<float>(s, kt);
+}
+
+template <typename T>
+hipError_t enqueue_diag_t(gpe_state* s) {
+  gpe::DiagArgs<T> d;
+  d.g = s->grid;
+  d.axisym = s->axi ? 1 : 0;
+  d.rho_l = s->P.rho_l;
+  d.rho_g = s->P.rho_g;
+  d.phi = buf<T>(s, B_PHI);
+  for (int q = 0; q < 4; ++q) d.q[q] = buf<T>(s, B_Q0 + q);
+  d.partial = buf<double>(s, B_SCR);
+  d.result = d.partial + gpe::kDiagBlocks * 8;
+  return gpe::launch_diag<T>(d, s->stream);
+}
+
+int run_diag(gpe_state* s, double out[8]) {
+  hipError_t e = s->P.precision == GPE_FP64 ? enqueue_diag_t<double>(s) : enqueue_diag_t<float>(s);
+  if (e != hipSuccess) return GPE_EHIP;
+  const double* res = buf<double>(s, B_SCR) + gpe::kDiagBlocks * 8;
+  if (hipMemcpyAsync(out, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+    return GPE_EHIP;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return GPE_EHIP;
+  return GPE_OK;
+}
+
+// External field id -> internal buffer.
+int field_buf(const gpe_state* s, int field) {
+  switch (field) {
+    case GPE_FIELD_P: return B_Q0 + 0;
+    case GPE_FIELD_U: return B_Q0 + 1;
+    case GPE_FIELD_V: return s->dim == 3 ? B_Q0 + 2 : B_Q0 + 3;
+    case GPE_FIELD_W: return s->dim == 3 ? B_Q0 + 3 : -1;
+    case GPE_FIELD_PHI: return B_PHI;
+  }
+  return -1;
+}
+
+template <typename T>
+int copy_t(gpe_state* s, int b, int dir, double* host) {
+  T* dev = buf<T>(s, b);
+  const size_t n = s->ncell;
+  if (sizeof(T) == sizeof(double)) {
+    hipError_t e = dir == GPE_H2D
+                       ? hipMemcpyAsync(dev, host, n * sizeof(T), hipMemcpyHostToDevice, s->stream)
+                       : hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) return GPE_EHIP;
+    return GPE_OK;
+  }
+  std::vector<T> tmp(n);
+  if (dir == GPE_H2D) {
+    for (size_t c = 0; c < n; ++c) tmp[c] = T(host[c]);
+    if (hipMemcpyAsync(dev, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return GPE_EHIP;
+  } else {
+    if (hipMemcpyAsync(tmp.data(), dev, n * sizeof(T), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return GPE_EHIP;
+    for (size_t c = 0; c < n; ++c) host[c] = (double)tmp[c];
+  }
+  return GPE_OK;
+}
+
+template <typename T>
+int init_fields_t(gpe_state* s, const double* h_phi0, const double* h_p0) {
+  const gpe_params& P = s->P;
+  gpe::InitArgs<T> a;
+  for (int q = 0; q < 3; ++q) a.n[q] = s->grid.n[q];
+  a.kind = h_phi0 ? 0 : P.init_kind;
+  a.has_y = s->dim == 3;
+  if (s->dim == 3) {
+    for (int q = 0; q < 3; ++q) a.center[q] = P.init_center[q];
+  } else {
+    a.center[0] = P.init_center[0];
+    a.center[1] = 0.0;
+    a.center[2] = P.init_center[1];
+  }
+  a.radius = P.init_radius;
+  a.width = P.init_width > 0 ? P.init_width : P.width;
+  a.amp = P.init_amp;
+  a.phi = buf<T>(s, B_PHI);
+  for (int q = 0; q < 4; ++q) a.q[q] = buf<T>(s, B_Q0 + q);
+  if (gpe::launch_init<T>(a, s->stream) != hipSuccess) return GPE_EHIP;
+  if (h_phi0) {
+    int r = copy_t<T>(s, B_PHI, GPE_H2D, const_cast<double*>(h_phi0));
+    if (r) return r;
+  }
+  if (h_p0) {
+    int r = copy_t<T>(s, B_Q0, GPE_H2D, const_cast<double*>(h_p0));
+    if (r) return r;
+  }
+  return GPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out) {
+  if (!in || !out) return GPE_EINVAL;
+  if (!(in->N_L > 0) || !(in->N_t > 0) || !(in->r_rho > 0) || !(in->r_eta > 0) || !(in->Re > 0))
+    return GPE_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->geometry = in->geometry;
+  out->precision = in->precision;
+  for (int a = 0; a < 3; ++a) out->n[a] = in->n[a];
+  for (int a = 0; a < 6; ++a) out->bc[a] = in->bc[a];
+  out->lattice = in->lattice;
+  // dx = L_c / N_L = 1, dt = T_c / N_t = 1, U_c = L_c / T_c = N_L / N_t
+  const double Uc = in->N_L / in->N_t;
+  out->dt = 1.0;
+  out->cs2 = 1.0 / 3.0;  // c_s = dx / (sqrt(3) dt)
+  out->rho_l = 1.0;
+  out->rho_g = 1.0 / in->r_rho;
+  out->eta_l = out->rho_l * Uc * in->N_L / in->Re;
+  out->eta_g = out->eta_l / in->r_eta;
+  if (in->capillary_scale)
+    out->sigma = Uc * out->eta_l;  // U_c = sigma / eta_L
+  else
+    out->sigma = in->We > 0 ? out->rho_l * Uc * Uc * in->N_L / in->We : 0.0;
+  out->mobility = in->Pe > 0 ? Uc * in->N_L * in->N_L / in->Pe : 0.0;  // sigma_ref = 1
+  out->width = in->Cn * in->N_L;
+  for (int a = 0; a < 3; ++a) out->g[a] = in->G[a] * Uc * Uc / in->N_L;
+  out->rho_ref = in->rho_ref_kind == 1 ? out->rho_l : (in->rho_ref_kind == 2 ? out->rho_g : 0.0);
+  return validate(out) == GPE_OK ? GPE_OK : GPE_EINVAL;
+}
+
+size_t gpe_workspace_bytes(const gpe_params* p) {
+  if (validate(p) != GPE_OK) return 0;
+  const size_t esize = p->precision == GPE_FP64 ? 8 : 4;
+  const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+  bool need[B_COUNT];
+  needed(p, need);
+  size_t total = 0;
+  for (int b = 0; b < B_SCR; ++b)
+    if (need[b]) total += align_up(ncell * esize);
+  total += align_up(scratch_bytes());
+  return total;
+}
+
+int gpe_init_state(const gpe_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+                   const double* h_phi0, const double* h_p0, gpe_state** out) {
+  if (!out) return GPE_EINVAL;
+  *out = nullptr;
+  int v = validate(p);
+  if (v) return v;
+  if (!p->allow_unstable && stability_ratio(p) > 1.0) return GPE_EUNSTABLE;
+  const size_t need_bytes = gpe_workspace_bytes(p);
+  if (!d_workspace || bytes < need_bytes || ((uintptr_t)d_workspace % kAlign) != 0)
+    return GPE_EWORKSPACE;
+  gpe_state* s = new (std::nothrow) gpe_state();
+  if (!s) return GPE_EINVAL;
+  s->P = *p;
+  s->dim = dim_of(p);
+  s->axi = p->geometry == GPE_GEOM_AXISYM;
+  s->esize = p->precision == GPE_FP64 ? 8 : 4;
+  s->ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+  s->stream = (hipStream_t)hip_stream;
+  s->ws = (char*)d_workspace;
+  s->ws_bytes = bytes;
+  s->step = 0;
+  s->t = 0.0;
+  s->sticky = GPE_OK;
+  s->graph_ok = false;
+  // internal grid: 3-D as is; 2-D / axisymmetric as (Z = y) x (X = x)
+  if (s->dim == 3) {
+    for (int a = 0; a < 3; ++a) s->grid.n[a] = p->n[a];
+    for (int a = 0; a < 6; ++a) s->grid.bc[a] = p->bc[a];
+  } else {
+    s->grid.n[0] = p->n[0];
+    s->grid.n[1] = 1;
+    s->grid.n[2] = p->n[1];
+    s->grid.bc[0] = p->bc[0];
+    s->grid.bc[1] = p->bc[1];
+    s->grid.bc[2] = s->grid.bc[3] = GPE_BC_PERIODIC;
+    s->grid.bc[4] = p->bc[2];
+    s->grid.bc[5] = p->bc[3];
+  }
+  s->grid.zchunk = 1;
+  bool need[B_COUNT];
+  needed(p, need);
+  size_t o = 0;
+  for (int b = 0; b < B_SCR; ++b) {
+    if (need[b]) {
+      s->off[b] = o;
+      o += align_up(s->ncell * s->esize);
+    } else {
+      s->off[b] = (size_t)-1;
+    }
+  }
+  s->off[B_SCR] = o;
+  int r = p->precision == GPE_FP64 ? init_fields_t<double>(s, h_phi0, h_p0)
+                                   : init_fields_t<float>(s, h_phi0, h_p0);
+  double d[8];
+  if (!r) r = run_diag(s, d);
+  if (r) {
+    delete s;
+    return r;
+  }
+  s->mass_abs0 = d[1];
+  *out = s;
+  return GPE_OK;
+}
+
+int gpe_rk3_step(gpe_state* s) {
+  if (!s) return GPE_EINVAL;
+  if (enqueue_step(s) != hipSuccess) return GPE_EHIP;
+  s->step += 1;
+  s->t = s->step * s->P.dt;
+  return GPE_OK;
+}
+
+int gpe_run_n(gpe_state* s, int64_t n) {
+  if (!s || n < 0) return GPE_EINVAL;
+  if (n == 0) return GPE_OK;
+  if (s->stream == nullptr || n < 2) {
+    for (int64_t q = 0; q < n; ++q)
+      if (enqueue_step(s) != hipSuccess) return GPE_EHIP;
+  } else {
+    if (!s->graph_ok) {
+      hipGraph_t gr;
+      if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return GPE_EHIP;
+      hipError_t e = enqueue_step(s);
+      hipError_t e2 = hipStreamEndCapture(s->stream, &gr);
+      if (e != hipSuccess || e2 != hipSuccess) return GPE_EHIP;
+      e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) return GPE_EHIP;
+      s->graph_ok = true;
+    }
+    for (int64_t q = 0; q < n; ++q)
+      if (hipGraphLaunch(s->graph, s->stream) != hipSuccess) return GPE_EHIP;
+  }
+  s->step += n;
+  s->t = s->step * s->P.dt;
+  return GPE_OK;
+}
+
+int gpe_diagnostics(gpe_state* s, gpe_diag* out) {
+  if (!s || !out) return GPE_EINVAL;
+  double d[8];
+  int r = run_diag(s, d);
+  if (r) return r;
+  out->step = s->step;
+  out->t = s->t;
+  out->mass = d[0];
+  out->mass_abs0 = s->mass_abs0;
+  out->ke = d[2];
+  out->max_div = d[3];
+  out->phi_min = -d[4];
+  out->phi_max = d[5];
+  out->umax = d[6];
+  out->finite = d[7] == 0.0 ? 1 : 0;
+  out->reserved = 0;
+  if (!out->finite) s->sticky = GPE_ENONFINITE;
+  return s->sticky;
+}
+
+int gpe_copy_field(gpe_state* s, int field, int dir, void* host, size_t bytes) {
+  if (!s || !host || (dir != GPE_H2D && dir != GPE_D2H)) return GPE_EINVAL;
+  const int b = field_buf(s, field);
+  if (b < 0) return GPE_EINVAL;
+  if (bytes != s->ncell * sizeof(double)) return GPE_EINVAL;
+  return s->P.precision == GPE_FP64 ? copy_t<double>(s, b, dir, (double*)host)
+                                    : copy_t<float>(s, b, dir, (double*)host);
+}
+
+size_t gpe_field_offset(const gpe_state* s, int field) {
+  if (!s) return (size_t)-1;
+  const int b = field_buf(s, field);
+  return b < 0 ? (size_t)-1 : s->off[b];
+}
+
+int gpe_set_step_time(gpe_state* s, int64_t step, double t) {
+  if (!s || step < 0) return GPE_EINVAL;
+  s->step = step;
+  s->t = t;
+  return GPE_OK;
+}
+
+int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, double* ms,
+                     double* bytes) {
+  if (!s || nsteps < 1 || max < 1 || !names || !ms || !bytes) return GPE_EINVAL;
+  const int nk = s->dim == 3 ? 7 : 5;
+  if (max < nk) return GPE_EINVAL;
+  static const char* n3[7] = {"flow_stage1", "flow_stage2", "flow_stage3", "ch_rk4_stage1",
+                              "ch_rk4_stage2", "ch_rk4_stage3", "ch_rk4_stage4"};
+  static const char* n2[5] = {"flow_stage1", "flow_stage2", "flow_stage3", "ch_rk2_stage1",
+                              "ch_rk2_stage2"};
+  // algorithmic HBM traffic per launch, in fields of one cell
+  const int d = s->dim;
+  const double f3[7] = {9, 13, 16, 6, 8, 8, 6};
+  const double f2[5] = {7, 10, 12, 4, 5};
+  (void)d;
+  KernelTimer kt;
+  kt.on = true;
+  for (int q = 0; q < 2 * nk; ++q)
+    if (hipEventCreate(&kt.ev[q]) != hipSuccess) return GPE_EHIP;
+  std::vector<double> acc(nk, 0.0);
+  int rc = GPE_OK;
+  for (int64_t st = 0; st < nsteps && rc == GPE_OK; ++st) {
+    kt.n = 0;
+    if (enqueue_step(s, &kt) != hipSuccess) { rc = GPE_EHIP; break; }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) { rc = GPE_EHIP; break; }
+    for (int q = 0; q < nk; ++q) {
+      float t = 0;
+      (void)hipEventElapsedTime(&t, kt.ev[2 * q], kt.ev[2 * q + 1]);
+      acc[q] += t;
+    }
+    s->step += 1;
+  }
+  s->t = s->step * s->P.dt;
+  for (int q = 0; q < 2 * nk; ++q) (void)hipEventDestroy(kt.ev[q]);
+  if (rc) return rc;
+  for (int q = 0; q < nk; ++q) {
+    names[q] = s->dim == 3 ? n3[q] : n2[q];
+    ms[q] = acc[q] / nsteps;
+    bytes[q] = (s->dim == 3 ? f3[q] : f2[q]) * (double)s->ncell * (double)s->esize;
+  }
+  return nk;
+}
+
+void gpe_destroy(gpe_state* s) {
+  if (!s) return;
+  if (s->graph_ok) (void)hipGraphExecDestroy(s->graph);
+  delete s;
+}
+
+const char* gpe_strerror(int code) {
+  switch (code) {
+    case GPE_OK: return "ok";
+    case GPE_EINVAL: return "invalid argument";
+    case GPE_EUNSTABLE: return "time step exceeds a linear stability estimate";
+    case GPE_EWORKSPACE: return "workspace too small or misaligned";
+    case GPE_EHIP: return "HIP runtime error";
+    case GPE_ENONFINITE: return "state is not finite";
+  }
+  return "unknown error";
+}
+
+}  // extern "C"

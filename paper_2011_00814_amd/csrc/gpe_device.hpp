@@ -1,0 +1,150 @@
+// gpe_device.hpp -- internal types and device helpers shared by the kernels
+// of libgpe (gfx950).  Not part of the public ABI.
+//
+// Internal axes: X (contiguous), Y (second in-plane axis, 3-D only) and Z,
+// the axis every stencil kernel marches along.  2-D and axisymmetric grids
+// are stored as (Z = physical y) x (X = physical x) with no Y axis, so one
+// kernel template covers all three geometries: in axisymmetric geometry Z is
+// the radial coordinate.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpe {
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_SYMMETRY = 2 };
+
+// Grid description in internal axis order.
+struct Grid {
+  int n[3];    // cells along X, Y, Z (n[1] = 1 in 2-D)
+  int bc[6];   // X-lo, X-hi, Y-lo, Y-hi, Z-lo, Z-hi
+  int zchunk;  // output planes per work-group along Z
+};
+
+// Constants in the working precision.
+template <typename T>
+struct Consts {
+  T dt, cs2;
+  T rho_l, rho_g, eta_l, eta_g;
+  T sigma, mob;
+  T a4;      // 4 a,  a = 3 / (4 W)
+  T kappa6;  // 6 kappa, kappa = 3 W / 8
+  T rho_ref;
+  T g[3];    // body force, internal axis order
+  T w1, w2, w3;  // lattice weights of links with 1, 2, 3 non-zero components
+};
+
+template <typename T>
+struct FlowArgs {
+  Grid g;
+  Consts<T> c;
+  const T* src[4];  // stage input (p, uX, uY, uZ)
+  const T* qn[4];   // time level n (read pointwise in stages 2 and 3)
+  T* dst[4];        // stage output; aliases qn in stage 3 (pointwise update)
+  const T* phi;     // frozen phase field
+  T* usum[3];       // stage 3: u^n + u^{n+1} on each face family
+};
+
+enum ChStage { CH_RK2_1 = 0, CH_RK2_2 = 1, CH_RK4_1 = 2, CH_RK4_2 = 3, CH_RK4_3 = 4, CH_RK4_4 = 5 };
+
+template <typename T>
+struct ChArgs {
+  Grid g;
+  Consts<T> c;
+  const T* phi_in;  // phase field the RHS is evaluated on (read with halo 2)
+  const T* usum[3]; // u^n + u^{n+1} on faces (centre velocity = 1/4 of the face pair sum)
+  const T* phis;    // phi* (start of the sub-step), read pointwise
+  T* acc;           // RK4 running sum phi* + sum b_i k_i
+  T* out;           // next stage input or the new phi*
+};
+
+// ---------------------------------------------------------------------------
+// Ghost rules: walls, symmetry planes and the axis lie on cell faces.
+// Cell-centred scalars are mirrored; the boundary-normal velocity is 0 on the
+// boundary face and odd across it; tangential velocity is odd across a
+// no-slip wall and even across a symmetry plane; periodic axes wrap.
+// ---------------------------------------------------------------------------
+
+// Cell index c (-2 <= c <= n+1) along an axis.  refl receives the BC of the
+// mirror crossed (0 if none).
+__device__ __forceinline__ int map_cell(int c, int n, int lo, int hi, int& refl) {
+  refl = 0;
+  if (c < 0) {
+    if (lo == BC_PERIODIC) return c + n;
+    refl = lo;
+    return -1 - c;
+  }
+  if (c >= n) {
+    if (hi == BC_PERIODIC) return c - n;
+    refl = hi;
+    return 2 * n - 1 - c;
+  }
+  return c;
+}
+
+// Face index f along its own normal axis.  sign becomes 0 for a boundary
+// face, -1 for a mirrored face.  The returned index is always in range.
+__device__ __forceinline__ int map_face(int f, int n, int lo, int& sign) {
+  sign = 1;
+  if (lo == BC_PERIODIC) {
+    if (f < 0) return f + n;
+    if (f >= n) return f - n;
+    return f;
+  }
+  if (f <= 0) {
+    if (f == 0) { sign = 0; return 0; }
+    sign = -1;
+    return -f;
+  }
+  if (f >= n) {
+    if (f == n) { sign = 0; return 0; }
+    sign = -1;
+    return 2 * n - f;
+  }
+  return f;
+}
+
+template <typename T>
+__device__ __forceinline__ T clamp1(T x) {
+  return fmin(fmax(x, T(-1)), T(1));
+}
+
+template <typename T>
+__device__ __forceinline__ T rho_of(const Consts<T>& c, T phi) {
+  T f = clamp1(phi);
+  return T(0.5) * (c.rho_l * (T(1) + f) + c.rho_g * (T(1) - f));
+}
+
+template <typename T>
+__device__ __forceinline__ T eta_of(const Consts<T>& c, T phi) {
+  T f = clamp1(phi);
+  return T(0.5) * (c.eta_l * (T(1) + f) + c.eta_g * (T(1) - f));
+}
+
+// Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Launchers (explicitly instantiated for float and double).
+template <typename T>
+hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, hipStream_t s);
+template <typename T>
+hipError_t launch_ch(const ChArgs<T>& a, int geometry, int stage, hipStream_t s);
+
+// Work-group tile shapes (X x Y columns, marched along Z).
+template <int DIM>
+struct FlowTile;
+template <>
+struct FlowTile<2> { static constexpr int TX = 64, TY = 1, ZC = 16; };
+template <>
+struct FlowTile<3> { static constexpr int TX = 32, TY = 8, ZC = 32; };
+
+template <int DIM>
+struct ChTile;
+template <>
+struct ChTile<2> { static constexpr int TX = 64, TY = 1, ZC = 16; };
+template <>
+struct ChTile<3> { static constexpr int TX = 32, TY = 8, ZC = 32; };
+
+}  // namespace gpe

@@ -1,0 +1,162 @@
+// gpe_misc.hip -- in-kernel initial condition and the diagnostics
+// reductions (phase mass, kinetic energy, max |div u|, phi range, max |u|,
+// finiteness).  Reductions accumulate in FP64 in both precisions, in a fixed
+// partition and order, so results are bitwise reproducible.
+#include "gpe_misc.hpp"
+
+namespace gpe {
+
+template <typename T>
+__global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
+  const size_t ncell = (size_t)a.n[0] * a.n[1] * a.n[2];
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % a.n[0]);
+    const int j = (int)((c / a.n[0]) % a.n[1]);
+    const int k = (int)(c / ((size_t)a.n[0] * a.n[1]));
+    const double x = i + 0.5, y = j + 0.5, z = k + 0.5;
+    double ph = a.amp;
+    if (a.kind == 1 || a.kind == 2) {
+      const double dx = x - a.center[0], dy = y - a.center[1], dz = z - a.center[2];
+      const double r = sqrt(dx * dx + (a.has_y ? dy * dy : 0.0) + dz * dz);
+      const double d = (a.kind == 1) ? (a.radius - r) : (r - a.radius);
+      ph = tanh(2.0 * d / a.width);
+    } else if (a.kind == 3) {
+      const double z0 = a.center[2] + a.amp * cos(2.0 * 3.14159265358979323846 * x / a.n[0]);
+      ph = tanh(2.0 * (z - z0) / a.width);
+    }
+    a.phi[c] = T(ph);
+    for (int f = 0; f < 4; ++f)
+      if (a.q[f]) a.q[f][c] = T(0);
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// slots: 0 mass, 1 sum|phi|, 2 ke, 3 max|div|, 4 min phi (stored negated as
+// a max), 5 max phi, 6 max|u|, 7 non-finite count
+template <typename T>
+__global__ __launch_bounds__(256) void diag_partial_kernel(DiagArgs<T> a) {
+  const Grid& g = a.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const size_t ncell = (size_t)nx * ny * nz;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY, 0.0, 0.0};
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx);
+    const int j = (int)((c / nx) % ny);
+    const int k = (int)(c / ((size_t)nx * ny));
+    const double ph = (double)a.phi[c];
+    const double wr = a.axisym ? (k + 0.5) : 1.0;
+    acc[0] += wr * ph;
+    acc[1] += wr * fabs(ph);
+    acc[4] = fmax(acc[4], -ph);
+    acc[5] = fmax(acc[5], ph);
+    bool fin = isfinite(ph) && isfinite((double)a.q[0][c]);
+    const double rho_c = 0.5 * (a.rho_l * (1.0 + fmin(fmax(ph, -1.0), 1.0)) +
+                                a.rho_g * (1.0 - fmin(fmax(ph, -1.0), 1.0)));
+    double div = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+      if (!a.q[1 + ax]) continue;
+      const double uf = (double)a.q[1 + ax][c];
+      fin = fin && isfinite(uf);
+      acc[6] = fmax(acc[6], fabs(uf));
+      // density at the low face: mean of the two adjacent cells
+      int idx[3] = {i, j, k};
+      idx[ax] -= 1;
+      int refl;
+      idx[ax] = map_cell(idx[ax], g.n[ax], g.bc[2 * ax], g.bc[2 * ax + 1], refl);
+      const double phl = (double)a.phi[((size_t)idx[2] * ny + idx[1]) * nx + idx[0]];
+      const double fl = fmin(fmax(phl, -1.0), 1.0);
+      const double rho_l = 0.5 * (a.rho_l * (1.0 + fl) + a.rho_g * (1.0 - fl));
+      const double rho_f = 0.5 * (rho_l + rho_c);
+      const double wf = (a.axisym && ax == 2) ? (double)k : wr;
+      acc[2] += 0.5 * rho_f * uf * uf * wf;
+      // high face value for the divergence
+      int hi[3] = {i, j, k};
+      int sgn;
+      hi[ax] = map_face(hi[ax] + 1, g.n[ax], g.bc[2 * ax], sgn);
+      const double uh = sgn * (double)a.q[1 + ax][((size_t)hi[2] * ny + hi[1]) * nx + hi[0]];
+      if (a.axisym && ax == 2)
+        div += ((k + 1.0) * uh - (double)k * uf) / (k + 0.5);
+      else
+        div += uh - uf;
+    }
+    acc[3] = fmax(acc[3], fabs(div));
+    if (!fin) acc[7] += 1.0;
+  }
+  __shared__ double red[4][8];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  double r[8];
+  r[0] = wave_sum(acc[0]); r[1] = wave_sum(acc[1]); r[2] = wave_sum(acc[2]);
+  r[3] = wave_max(acc[3]); r[4] = wave_max(acc[4]); r[5] = wave_max(acc[5]);
+  r[6] = wave_max(acc[6]); r[7] = wave_sum(acc[7]);
+  if (lane == 0)
+    for (int s = 0; s < 8; ++s) red[wv][s] = r[s];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o[8];
+    for (int s = 0; s < 8; ++s) o[s] = red[0][s];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
+      o[0] += red[w][0]; o[1] += red[w][1]; o[2] += red[w][2];
+      o[3] = fmax(o[3], red[w][3]); o[4] = fmax(o[4], red[w][4]);
+      o[5] = fmax(o[5], red[w][5]); o[6] = fmax(o[6], red[w][6]);
+      o[7] += red[w][7];
+    }
+    for (int s = 0; s < 8; ++s) a.partial[(size_t)blockIdx.x * 8 + s] = o[s];
+  }
+}
+
+__global__ __launch_bounds__(64) void diag_final_kernel(const double* partial, int nblk, double* out) {
+  // one wave: lane l folds partials l, l+64, ... in order, then a fixed tree
+  const int l = threadIdx.x;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY, 0.0, 0.0};
+  for (int b = l; b < nblk; b += 64) {
+    const double* p = partial + (size_t)b * 8;
+    acc[0] += p[0]; acc[1] += p[1]; acc[2] += p[2];
+    acc[3] = fmax(acc[3], p[3]); acc[4] = fmax(acc[4], p[4]);
+    acc[5] = fmax(acc[5], p[5]); acc[6] = fmax(acc[6], p[6]);
+    acc[7] += p[7];
+  }
+  double r[8];
+  r[0] = wave_sum(acc[0]); r[1] = wave_sum(acc[1]); r[2] = wave_sum(acc[2]);
+  r[3] = wave_max(acc[3]); r[4] = wave_max(acc[4]); r[5] = wave_max(acc[5]);
+  r[6] = wave_max(acc[6]); r[7] = wave_sum(acc[7]);
+  if (l == 0)
+    for (int s = 0; s < 8; ++s) out[s] = r[s];
+}
+
+template <typename T>
+hipError_t launch_init(const InitArgs<T>& a, hipStream_t s) {
+  const size_t ncell = (size_t)a.n[0] * a.n[1] * a.n[2];
+  const unsigned blocks = (unsigned)std::min<size_t>((ncell + 255) / 256, 16384);
+  hipLaunchKernelGGL((init_kernel<T>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diag(const DiagArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((diag_partial_kernel<T>), dim3(kDiagBlocks), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, a.partial, kDiagBlocks, a.result);
+  return hipGetLastError();
+}
+
+template hipError_t launch_init<float>(const InitArgs<float>&, hipStream_t);
+template hipError_t launch_init<double>(const InitArgs<double>&, hipStream_t);
+template hipError_t launch_diag<float>(const DiagArgs<float>&, hipStream_t);
+template hipError_t launch_diag<double>(const DiagArgs<double>&, hipStream_t);
+
+}  // namespace gpe

@@ -1,0 +1,296 @@
+"""Thin ctypes binding of libgpe (include/gpe.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libgpe.so; PyTorch only
+provides the device workspace and the stream.  Importing this module does not
+load the library; the first call does, and fails loudly when the library has
+not been built (``python -m paper_2011_00814_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libgpe.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gpe.h")
+
+GPE_OK, GPE_EINVAL, GPE_EUNSTABLE, GPE_EWORKSPACE, GPE_EHIP, GPE_ENONFINITE = 0, -1, -2, -3, -4, -5
+GPE_GEOM_2D, GPE_GEOM_AXISYM, GPE_GEOM_3D = 0, 1, 2
+GPE_FP64, GPE_FP32 = 0, 1
+GPE_FIELD_P, GPE_FIELD_U, GPE_FIELD_V, GPE_FIELD_W, GPE_FIELD_PHI = 0, 1, 2, 3, 4
+GPE_H2D, GPE_D2H = 0, 1
+GPE_INIT_NONE, GPE_INIT_DROP, GPE_INIT_BUBBLE, GPE_INIT_LAYER = 0, 1, 2, 3
+
+i32, f64 = ctypes.c_int32, ctypes.c_double
+
+
+class gpe_params(ctypes.Structure):
+    _fields_ = [
+        ("geometry", i32), ("precision", i32), ("n", i32 * 3), ("bc", i32 * 6),
+        ("lattice", i32), ("allow_unstable", i32), ("reserved0", i32), ("dt", f64), ("cs2", f64),
+        ("rho_l", f64), ("rho_g", f64), ("eta_l", f64), ("eta_g", f64),
+        ("sigma", f64), ("mobility", f64), ("width", f64), ("g", f64 * 3), ("rho_ref", f64),
+        ("init_kind", i32), ("reserved", i32), ("init_center", f64 * 3), ("init_radius", f64),
+        ("init_width", f64), ("init_amp", f64),
+    ]
+
+
+class gpe_problem(ctypes.Structure):
+    _fields_ = [
+        ("geometry", i32), ("precision", i32), ("n", i32 * 3), ("bc", i32 * 6),
+        ("lattice", i32), ("capillary_scale", i32), ("reserved0", i32), ("N_L", f64), ("N_t", f64),
+        ("r_rho", f64), ("r_eta", f64), ("Re", f64), ("We", f64), ("Pe", f64), ("Cn", f64),
+        ("G", f64 * 3), ("rho_ref_kind", i32), ("reserved", i32),
+    ]
+
+
+class gpe_diag(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("t", f64), ("mass", f64), ("mass_abs0", f64), ("ke", f64),
+        ("max_div", f64), ("phi_min", f64), ("phi_max", f64), ("umax", f64),
+        ("finite", i32), ("reserved", i32),
+    ]
+
+
+class GpeError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {gpe_strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/gpe.h."""
+    src = open(HEADER).read()
+    return re.findall(r"^\s*(?:int|size_t|void|const char\*)\s+(gpe_\w+)\s*\(", src, re.M)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2011_00814_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.gpe_params_from_dimensionless.argtypes = [ctypes.POINTER(gpe_problem), ctypes.POINTER(gpe_params)]
+        L.gpe_params_from_dimensionless.restype = ctypes.c_int
+        L.gpe_workspace_bytes.argtypes = [ctypes.POINTER(gpe_params)]
+        L.gpe_workspace_bytes.restype = sz
+        L.gpe_init_state.argtypes = [ctypes.POINTER(gpe_params), vp, sz, vp, vp, vp, ctypes.POINTER(vp)]
+        L.gpe_init_state.restype = ctypes.c_int
+        L.gpe_rk3_step.argtypes = [vp]
+        L.gpe_rk3_step.restype = ctypes.c_int
+        L.gpe_run_n.argtypes = [vp, ctypes.c_int64]
+        L.gpe_run_n.restype = ctypes.c_int
+        L.gpe_diagnostics.argtypes = [vp, ctypes.POINTER(gpe_diag)]
+        L.gpe_diagnostics.restype = ctypes.c_int
+        L.gpe_copy_field.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, sz]
+        L.gpe_copy_field.restype = ctypes.c_int
+        L.gpe_field_offset.argtypes = [vp, ctypes.c_int]
+        L.gpe_field_offset.restype = sz
+        L.gpe_set_step_time.argtypes = [vp, ctypes.c_int64, f64]
+        L.gpe_set_step_time.restype = ctypes.c_int
+        L.gpe_kernel_times.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                       ctypes.POINTER(f64), ctypes.POINTER(f64)]
+        L.gpe_kernel_times.restype = ctypes.c_int
+        L.gpe_destroy.argtypes = [vp]
+        L.gpe_destroy.restype = None
+        L.gpe_strerror.argtypes = [ctypes.c_int]
+        L.gpe_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+# ---- functions with the names of the C-ABI ---------------------------------
+def gpe_strerror(code: int) -> str:
+    return lib().gpe_strerror(int(code)).decode()
+
+
+def gpe_params_from_dimensionless(problem: gpe_problem) -> gpe_params:
+    out = gpe_params()
+    rc = lib().gpe_params_from_dimensionless(ctypes.byref(problem), ctypes.byref(out))
+    if rc:
+        raise GpeError(rc, "gpe_params_from_dimensionless")
+    return out
+
+
+def gpe_workspace_bytes(params: gpe_params) -> int:
+    return int(lib().gpe_workspace_bytes(ctypes.byref(params)))
+
+
+def gpe_init_state(params, d_workspace: int, nbytes: int, stream: int, h_phi0=None, h_p0=None):
+    handle = ctypes.c_void_p()
+    phi = None if h_phi0 is None else np.ascontiguousarray(h_phi0, dtype=np.float64)
+    p0 = None if h_p0 is None else np.ascontiguousarray(h_p0, dtype=np.float64)
+    rc = lib().gpe_init_state(ctypes.byref(params), ctypes.c_void_p(d_workspace), nbytes,
+                              ctypes.c_void_p(stream),
+                              None if phi is None else phi.ctypes.data_as(ctypes.c_void_p),
+                              None if p0 is None else p0.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.byref(handle))
+    if rc:
+        raise GpeError(rc, "gpe_init_state")
+    return handle
+
+
+def gpe_rk3_step(h):
+    rc = lib().gpe_rk3_step(h)
+    if rc:
+        raise GpeError(rc, "gpe_rk3_step")
+
+
+def gpe_run_n(h, n: int):
+    rc = lib().gpe_run_n(h, int(n))
+    if rc:
+        raise GpeError(rc, "gpe_run_n")
+
+
+def gpe_diagnostics(h, check=True) -> dict:
+    d = gpe_diag()
+    rc = lib().gpe_diagnostics(h, ctypes.byref(d))
+    if rc and (check or rc != GPE_ENONFINITE):
+        raise GpeError(rc, "gpe_diagnostics")
+    return {k: getattr(d, k) for k, _ in gpe_diag._fields_ if k != "reserved"}
+
+
+def gpe_copy_field(h, field: int, direction: int, host: np.ndarray):
+    assert host.dtype == np.float64 and host.flags["C_CONTIGUOUS"]
+    rc = lib().gpe_copy_field(h, int(field), int(direction), host.ctypes.data_as(ctypes.c_void_p),
+                              host.nbytes)
+    if rc:
+        raise GpeError(rc, "gpe_copy_field")
+
+
+def gpe_field_offset(h, field: int) -> int:
+    return int(lib().gpe_field_offset(h, int(field)))
+
+
+def gpe_set_step_time(h, step: int, t: float):
+    rc = lib().gpe_set_step_time(h, int(step), float(t))
+    if rc:
+        raise GpeError(rc, "gpe_set_step_time")
+
+
+def gpe_kernel_times(h, nsteps: int, maxk: int = 16):
+    names = (ctypes.c_char_p * maxk)()
+    ms = (f64 * maxk)()
+    nb = (f64 * maxk)()
+    rc = lib().gpe_kernel_times(h, int(nsteps), maxk, names, ms, nb)
+    if rc < 0:
+        raise GpeError(rc, "gpe_kernel_times")
+    return [(names[q].decode(), ms[q], nb[q]) for q in range(rc)]
+
+
+def gpe_destroy(h):
+    lib().gpe_destroy(h)
+
+
+# ---- problem dictionary -> gpe_params ----------------------------------------
+def params_from_problem(prob: dict) -> gpe_params:
+    P = gpe_params()
+    if prob["dim"] == 3:
+        P.geometry = GPE_GEOM_3D
+    else:
+        P.geometry = GPE_GEOM_AXISYM if prob.get("axisym") else GPE_GEOM_2D
+    P.precision = GPE_FP32 if prob.get("precision", "fp64") == "fp32" else GPE_FP64
+    for a in range(3):
+        P.n[a] = int(prob["n"][a])
+    for s in range(6):
+        P.bc[s] = int(prob["bc"][s])
+    P.lattice = int(prob["lattice"])
+    P.allow_unstable = int(prob.get("allow_unstable", 0))
+    P.dt, P.cs2 = float(prob["dt"]), float(prob["cs2"])
+    P.rho_l, P.rho_g = float(prob["rho_l"]), float(prob["rho_g"])
+    P.eta_l, P.eta_g = float(prob["eta_l"]), float(prob["eta_g"])
+    P.sigma, P.mobility, P.width = float(prob["sigma"]), float(prob["mob"]), float(prob["width"])
+    for a in range(3):
+        P.g[a] = float(prob["g"][a])
+    P.rho_ref = float(prob["rho_ref"])
+    init = prob.get("init")
+    if init:
+        P.init_kind = int(init["kind"])
+        for a in range(3):
+            P.init_center[a] = float(init.get("center", (0, 0, 0))[a])
+        P.init_radius = float(init.get("radius", 0.0))
+        P.init_width = float(init.get("width", prob["width"]))
+        P.init_amp = float(init.get("amp", 0.0))
+    return P
+
+
+class Solver:
+    """One simulation on one GPU: a torch-allocated workspace, a torch stream
+    and a libgpe handle.  Marshalling only."""
+
+    FIELDS = {"p": GPE_FIELD_P, "u": GPE_FIELD_U, "v": GPE_FIELD_V, "w": GPE_FIELD_W, "phi": GPE_FIELD_PHI}
+
+    def __init__(self, prob: dict, state: dict | None = None, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.prob = prob
+        self.params = params_from_problem(prob)
+        nbytes = gpe_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise GpeError(GPE_EINVAL, "gpe_workspace_bytes")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        nx, ny, nz = prob["n"]
+        self.shape = (nz, ny, nx)
+        phi0 = p0 = None
+        if state is not None:
+            phi0 = np.ascontiguousarray(state["phi"], dtype=np.float64).reshape(self.shape)
+            p0 = np.ascontiguousarray(state["p"], dtype=np.float64).reshape(self.shape)
+        self.h = gpe_init_state(self.params, self.ws_ptr, nbytes, self.stream.cuda_stream, phi0, p0)
+        if state is not None:
+            for key in ("u", "v") + (("w",) if prob["dim"] == 3 else ()):
+                if state.get(key) is not None and np.any(state[key]):
+                    self.set(key, state[key])
+
+    def rk3_step(self):
+        gpe_rk3_step(self.h)
+
+    def run(self, n: int):
+        gpe_run_n(self.h, n)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def diagnostics(self, check=True) -> dict:
+        return gpe_diagnostics(self.h, check)
+
+    def get(self, key: str) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        gpe_copy_field(self.h, self.FIELDS[key], GPE_D2H, out)
+        return out
+
+    def set(self, key: str, arr):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(self.shape))
+        gpe_copy_field(self.h, self.FIELDS[key], GPE_H2D, a)
+
+    def state(self) -> dict:
+        keys = ("p", "u", "v", "phi") + (("w",) if self.prob["dim"] == 3 else ())
+        st = {k: self.get(k) for k in keys}
+        if self.prob["dim"] != 3:
+            st["w"] = None
+        return st
+
+    def kernel_times(self, nsteps: int):
+        return gpe_kernel_times(self.h, nsteps)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            gpe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

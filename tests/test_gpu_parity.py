@@ -1,0 +1,263 @@
+"""GPU (HIP, gfx950) time step against the CPU FP64 oracle, through the C-ABI.
+
+Tolerances: FP64 relative L2 <= 1e-11 after up to 1000 steps, FP32 <= 1e-4
+on u, p, phi; FP32 phase-mass drift < 1e-6 (relative to sum |phi_0|).
+Sizes span several work-group tiles (X tile 32 in 3-D, 64 in 2-D; Y tile 8;
+Z chunks of 32 / 16 planes) with ragged tails.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2011_00814_amd import workloads as W
+from tests.parity_util import compare_states, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpe():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_00814_amd import gpe as G
+
+    G.lib()
+    return G
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run_gpu(G, prob, st, nsteps, graph=True):
+    s = G.Solver(prob, st)
+    if graph:
+        s.run(nsteps)
+    else:
+        for _ in range(nsteps):
+            s.rk3_step()
+    s.synchronize()
+    out = s.state()
+    d = s.diagnostics()
+    s.close()
+    return out, d
+
+
+def _check(prob, gpu, ref, tol, keys=None):
+    errs = compare_states(prob, gpu, ref)
+    keys = keys or list(errs)
+    bad = {k: v for k, v in errs.items() if k in keys and not v <= tol}
+    assert not bad, (errs, tol)
+    return errs
+
+
+# ---------------------------------------------------------------------------
+CASES = {
+    "drop2d_periodic": lambda: W.static_drop_2d(n=70, R=14.0),
+    "rt2d_walls": lambda: W.rayleigh_taylor_2d(nx=70, ny=150, amp_frac=0.05),
+    "axisym_drop": lambda: W.axisym_drop(nz=100, nr=37, R=10.0, zc=45.0),
+    "bubble3d_walls": lambda: W.rising_bubble_3d(nx=40, ny=19, nz=40, R=7.0, zc=17.0, precision="fp64"),
+}
+
+
+def _case(name, seed=1, precision="fp64"):
+    prob, st = CASES[name]()
+    prob = dict(prob, precision=precision)
+    if name == "rt2d_walls":
+        prob["g"] = (0.0, -2e-4, 0.0)
+    if name == "bubble3d_walls":
+        prob["g"] = (0.0, 0.0, -2e-4)
+    st = W.perturbed(prob, st, seed, uamp=2e-3, pamp=2e-4)
+    return prob, st
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("nsteps", [1, 40])
+def test_fp64_parity_short(gpe, oracle, name, nsteps):
+    prob, st = _case(name)
+    _say(f"[parity] {name} fp64 n={prob['n']} steps={nsteps}")
+    ref = oracle.run(prob, st, nsteps)
+    out, d = _run_gpu(gpe, prob, st, nsteps)
+    assert d["finite"] == 1
+    _check(prob, out, ref, 1e-12 if nsteps == 1 else 1e-11)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_parity(gpe, oracle, name):
+    prob, st = _case(name, precision="fp32")
+    nsteps = 40
+    _say(f"[parity] {name} fp32 n={prob['n']} steps={nsteps}")
+    ref = oracle.run(prob, st, nsteps)
+    out, d = _run_gpu(gpe, prob, st, nsteps)
+    _check(prob, out, ref, 1e-4, keys=["p", "u", "phi"])
+    drift = abs(d["mass"] - oracle.diagnostics(prob, st)["mass"]) / d["mass_abs0"]
+    assert drift < 1e-6
+
+
+def test_static_drop_fp64_1000_steps(gpe, oracle):
+    """Configuration 1 (64x64 periodic static drop) for 1000 steps."""
+    prob, st = W.static_drop_2d()
+    _say("[parity] static drop 64x64 fp64 1000 steps")
+    ref = oracle.run(prob, st, 1000)
+    out, d = _run_gpu(gpe, prob, st, 1000)
+    _check(prob, out, ref, 1e-11)
+    drift = abs(d["mass"] - oracle.diagnostics(prob, st)["mass"]) / d["mass_abs0"]
+    assert drift < 1e-13
+
+
+def test_static_drop_fp32_1000_steps(gpe, oracle):
+    prob, st = W.static_drop_2d(precision="fp32")
+    _say("[parity] static drop 64x64 fp32 1000 steps")
+    ref = oracle.run(prob, st, 1000)
+    out, d = _run_gpu(gpe, prob, st, 1000)
+    _check(prob, out, ref, 1e-4, keys=["p", "u", "phi"])
+    drift = abs(d["mass"] - oracle.diagnostics(prob, st)["mass"]) / d["mass_abs0"]
+    assert drift < 1e-6
+
+
+def test_bubble3d_fp64_200_steps(gpe, oracle):
+    prob, st = _case("bubble3d_walls")
+    _say("[parity] bubble3d fp64 200 steps")
+    ref = oracle.run(prob, st, 200)
+    out, _ = _run_gpu(gpe, prob, st, 200)
+    _check(prob, out, ref, 1e-11)
+
+
+@pytest.mark.parametrize("lat", [19, 27])
+def test_3d_lattices(gpe, oracle, lat):
+    prob, st = _case("bubble3d_walls")
+    prob["lattice"] = lat
+    prob["bc"] = (0, 0, 2, 2, 1, 1)
+    st = W.perturbed(prob, W.rising_bubble_3d(nx=40, ny=19, nz=40, R=7.0, zc=17.0,
+                                                precision="fp64")[1], 5, uamp=2e-3, pamp=2e-4)
+    _say(f"[parity] bubble3d D3Q{lat} mixed BCs")
+    ref = oracle.run(prob, st, 20)
+    out, _ = _run_gpu(gpe, prob, st, 20)
+    _check(prob, out, ref, 1e-11)
+
+
+def test_diagnostics_match_oracle(gpe, oracle):
+    for name in CASES:
+        prob, st = _case(name)
+        s = gpe.Solver(prob, st)
+        s.run(5)
+        s.synchronize()
+        d = s.diagnostics()
+        ref = oracle.diagnostics(prob, s.state())
+        s.close()
+        for k in ("mass", "ke", "max_div", "phi_min", "phi_max", "umax"):
+            assert abs(d[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), (name, k, d[k], ref[k])
+        assert d["finite"] == 1
+
+
+# ---------------------------------------------------------------------------
+# Execution-model properties: graph replay, determinism, checkpoint/resume,
+# failure detection.
+# ---------------------------------------------------------------------------
+def test_graph_replay_equals_eager_bitwise(gpe):
+    for name in ("drop2d_periodic", "bubble3d_walls"):
+        prob, st = _case(name)
+        a, _ = _run_gpu(gpe, prob, st, 12, graph=True)
+        b, _ = _run_gpu(gpe, prob, st, 12, graph=False)
+        for k in a:
+            if a[k] is not None:
+                assert np.array_equal(a[k], b[k]), (name, k)
+
+
+def test_checkpoint_resume_bitwise(gpe):
+    prob, st = _case("bubble3d_walls", precision="fp32")
+    full, _ = _run_gpu(gpe, prob, st, 16)
+    s = gpe.Solver(prob, st)
+    s.run(8)
+    s.synchronize()
+    mid = s.state()
+    s.close()
+    s2 = gpe.Solver(prob, mid)
+    gpe.gpe_set_step_time(s2.h, 8, 8.0)
+    s2.run(8)
+    s2.synchronize()
+    res = s2.state()
+    assert s2.diagnostics()["step"] == 16
+    s2.close()
+    for k in ("p", "u", "v", "w", "phi"):
+        assert np.array_equal(full[k], res[k]), k
+
+
+def test_nonfinite_detected(gpe):
+    prob, st = _case("drop2d_periodic")
+    s = gpe.Solver(prob, st)
+    phi = s.get("phi")
+    phi[3, 0, 5] = np.nan
+    s.set("phi", phi)
+    with pytest.raises(gpe.GpeError) as e:
+        s.diagnostics()
+    assert e.value.code == gpe.GPE_ENONFINITE
+    s.close()
+
+
+def test_unstable_rejected(gpe):
+    prob, st = W.static_drop_2d()
+    prob["mob"] = 0.2  # CH step far beyond the RK2 limit
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.Solver(prob, st)
+    assert e.value.code == gpe.GPE_EUNSTABLE
+
+
+def test_rest_state_bitwise_gpu(gpe):
+    for dim, bc in ((2, (1, 1, 2, 2, 0, 0)), (3, (1, 1, 0, 0, 2, 2))):
+        n = (70, 37, 1) if dim == 2 else (40, 19, 40)
+        prob = W.base_problem(dim=dim, n=n, bc=bc, rho_l=1.0, rho_g=0.2, eta_l=0.03, eta_g=0.01,
+                              sigma=0.01, mob=0.05, g=(1e-4, -2e-4, 3e-4 if dim == 3 else 0.0))
+        phi0 = 0.37
+        prob["rho_ref"] = 0.5 * (1.0 * (1 + phi0) + 0.2 * (1 - phi0))
+        st = W.zero_state(prob)
+        st["phi"][:] = phi0
+        st["p"][:] = 0.123
+        for prec in ("fp64", "fp32"):
+            pr = dict(prob, precision=prec)
+            out, _ = _run_gpu(gpe, pr, st, 25)
+            ref = {k: (None if v is None else v.astype(np.float32 if prec == "fp32" else np.float64))
+                   for k, v in st.items()}
+            for k in out:
+                if out[k] is not None:
+                    assert np.array_equal(out[k], ref[k].astype(np.float64)), (dim, prec, k)
+
+
+# ---------------------------------------------------------------------------
+# Full size, benchmark launch configuration: 256^3 rising bubble, FP32.
+# ---------------------------------------------------------------------------
+def test_full_size_256cubed_fp32_one_step(gpe, oracle):
+    prob, st = W.rising_bubble_3d(nx=256, ny=256, nz=256, zc=48.0, precision="fp32")
+    st = W.perturbed(prob, st, 7, uamp=2e-3, pamp=2e-4)
+    _say("[parity] 256^3 fp32 one step vs oracle")
+    out, d = _run_gpu(gpe, prob, st, 1, graph=False)
+    ref = oracle.run(prob, st, 1)
+    _check(prob, out, ref, 1e-4)
+    drift = abs(d["mass"] - oracle.diagnostics(prob, st)["mass"]) / d["mass_abs0"]
+    assert drift < 1e-6
+
+
+def test_full_size_256cubed_fp32_properties(gpe):
+    """Properties that hold at any size: phase mass conserved and the state
+    finite over 50 graph-replayed steps; bubble mirror-symmetric in x and y."""
+    prob, st = W.rising_bubble_3d(nx=256, ny=256, nz=256, zc=48.0, precision="fp32")
+    s = gpe.Solver(prob, st)
+    d0 = s.diagnostics()
+    s.run(50)
+    s.synchronize()
+    d1 = s.diagnostics()
+    assert d1["finite"] == 1
+    assert abs(d1["mass"] - d0["mass"]) / d0["mass_abs0"] < 1e-6
+    w = s.get("w")
+    phi = s.get("phi")
+    s.close()
+    assert d1["ke"] > 0
+    sc = np.max(np.abs(w))
+    assert np.max(np.abs(w - w[:, :, ::-1])) <= 1e-4 * sc
+    assert np.max(np.abs(w - w[:, ::-1, :])) <= 1e-4 * sc
+    assert np.max(np.abs(phi - phi[:, :, ::-1])) <= 1e-5
