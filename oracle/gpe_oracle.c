@@ -26,7 +26,8 @@
  *   - rho at a velocity point is the mean of the two adjacent cells.
  *   - the bulk term d/dx(eta D) pairs eta_i with D_i (same cell).
  *   - the factor 2 of d/dx(2 eta du/dx) multiplies the printed sub-stencil.
- *   - stencils are evaluated difference-first (sum of w (f_nb - f_c)).
+ *   - stencils are evaluated difference-first (sum of w (f_nb - f_c)), and
+ *     the Runge-Kutta combinations in increment form (see orc_run).
  *   - boundaries sit on cell faces; normal velocity there is 0; ghosts mirror
  *     scalars, negate the normal velocity, and negate (no-slip wall) or keep
  *     (symmetry plane, axis) the tangential velocity.
@@ -506,14 +507,18 @@ int orc_run(const orc_params* P, double* p, double* u, double* v, double* w,
       free(buf);
       return -1;
     }
+    /* The Shu-Osher combinations a q^n + (1 - a)(q^(s) + dt L) are written
+     * in the algebraically identical increment form
+     * q^n + (1 - a)((q^(s) - q^n) + dt L), which returns q^n exactly when
+     * the right-hand side vanishes (a steady state stays bitwise steady). */
     if (P->flags & ORC_FLOW_RK2) {
       for (int f = 0; f < nq; ++f)
         for (size_t c = 0; c < N; ++c)
-          q0[f][c] = 0.5 * q0[f][c] + 0.5 * (q1[f][c] + dt * Lq[f][c]);
+          q0[f][c] = q0[f][c] + 0.5 * ((q1[f][c] - q0[f][c]) + dt * Lq[f][c]);
     } else {
       for (int f = 0; f < nq; ++f)
         for (size_t c = 0; c < N; ++c)
-          q2[f][c] = 0.75 * q0[f][c] + 0.25 * (q1[f][c] + dt * Lq[f][c]);
+          q2[f][c] = q0[f][c] + 0.25 * ((q1[f][c] - q0[f][c]) + dt * Lq[f][c]);
       if (orc_flow_rhs(P, q2[0], QV(q2, 0), QV(q2, 1), dim == 3 ? QV(q2, 2) : NULL, phi,
                        Lq[0], QV(Lq, 0), QV(Lq, 1), dim == 3 ? QV(Lq, 2) : NULL)) {
         free(buf);
@@ -521,7 +526,7 @@ int orc_run(const orc_params* P, double* p, double* u, double* v, double* w,
       }
       for (int f = 0; f < nq; ++f)
         for (size_t c = 0; c < N; ++c)
-          q0[f][c] = q0[f][c] / 3.0 + 2.0 / 3.0 * (q2[f][c] + dt * Lq[f][c]);
+          q0[f][c] = q0[f][c] + 2.0 / 3.0 * ((q2[f][c] - q0[f][c]) + dt * Lq[f][c]);
     }
 
     /* ---- centre velocity at t^{n+1/2}: mean over the two faces of the cell
@@ -546,7 +551,7 @@ int orc_run(const orc_params* P, double* p, double* u, double* v, double* w,
       orc_ch_rhs(P, phi, uh[0], uh[1], w3, Lph);
       for (size_t c = 0; c < N; ++c) ph1[c] = phi[c] + dt * Lph[c];
       orc_ch_rhs(P, ph1, uh[0], uh[1], w3, Lph);
-      for (size_t c = 0; c < N; ++c) phi[c] = 0.5 * phi[c] + 0.5 * (ph1[c] + dt * Lph[c]);
+      for (size_t c = 0; c < N; ++c) phi[c] = phi[c] + 0.5 * ((ph1[c] - phi[c]) + dt * Lph[c]);
     } else {
       /* classic RK4: a, b, c, d increments; the sum (a + 2b + 2c + d)/6 */
       double* ka = acc;              /* a, then running weighted sum */

@@ -105,11 +105,16 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
     T* FZ = &lds[(S_FZ + slot3(m)) * PLANE];
     T rp = T(1), rm = T(1), rnode = T(1);
     if (AXI) {
+      // A ghost plane beyond the axis or the outer wall mirrors an in-domain
+      // row: use that row's radius, with the up/down link weights exchanged,
+      // so that mu on the ghost plane is the mirror image of mu on the row.
       const ZMap<T> z(g, m);
-      const T rk = T(m) + T(0.5);
-      rp = (rk + T(0.5)) / rk;
-      rm = (rk - T(0.5)) / rk;
-      rnode = z.r;  // radius of the in-domain row plane m mirrors
+      const T rk = z.r;
+      const T up = (rk + T(0.5)) / rk, dn = (rk - T(0.5)) / rk;
+      const bool mirrored = m < 0 || m >= nz;
+      rp = mirrored ? dn : up;
+      rm = mirrored ? up : dn;
+      rnode = rk;
     }
     constexpr int EXN = TX + 2;
     constexpr int EN = (DIM == 3) ? (TX + 2) * (TY + 2) : TX + 2;
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
         A.out[ci] = phc + dt * L;
       } else if (STAGE == CH_RK2_2) {
         const T ps = A.phis[ci];
-        A.out[ci] = T(0.5) * ps + T(0.5) * (phc + dt * L);
+        A.out[ci] = ps + T(0.5) * ((phc - ps) + dt * L);
       } else if (STAGE == CH_RK4_1) {
         const T kk = dt * L;
         A.out[ci] = phc + T(0.5) * kk;

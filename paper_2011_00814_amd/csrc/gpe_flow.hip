@@ -327,10 +327,11 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
           out[f] = q[f] + dt * L[f];
         } else {
           old[f] = A.qn[f][ci];
+          // Shu-Osher combination in increment form: exact for L = 0
           if (STAGE == 2)
-            out[f] = T(0.75) * old[f] + T(0.25) * (q[f] + dt * L[f]);
+            out[f] = old[f] + T(0.25) * ((q[f] - old[f]) + dt * L[f]);
           else
-            out[f] = old[f] * T(1.0 / 3.0) + T(2.0 / 3.0) * (q[f] + dt * L[f]);
+            out[f] = old[f] + T(2.0 / 3.0) * ((q[f] - old[f]) + dt * L[f]);
         }
       }
       if (bX) out[1] = T(0);

@@ -124,7 +124,7 @@ def axisym_drop(nz=96, nr=32, R=10.0, zc=40.0, precision="fp64"):
     prob = base_problem(
         dim=2, n=(nz, nr, 1), bc=(WALL, WALL, SYMMETRY, WALL, 0, 0),
         rho_l=1.0, rho_g=1.0 / 1.15, eta_l=0.02, eta_g=0.02, sigma=2e-3,
-        mob=0.05, width=3.0, g=(-1e-5, 0.0, 0.0), rho_ref=1.0 / 1.15,
+        mob=0.03, width=3.0, g=(-1e-5, 0.0, 0.0), rho_ref=1.0 / 1.15,
         precision=precision)
     prob["axisym"] = 1
     x, y, _ = _centres(prob)
