@@ -216,7 +216,7 @@ def test_rest_state_bitwise_gpu(gpe):
         # phi0 and the densities are binary fractions: rho(phi0) - rho_ref is
         # exactly 0 in FP32 as in FP64
         prob = W.base_problem(dim=dim, n=n, bc=bc, rho_l=1.0, rho_g=0.25, eta_l=0.03, eta_g=0.01,
-                              sigma=0.01, mob=0.05, g=(1e-4, -2e-4, 3e-4 if dim == 3 else 0.0))
+                              sigma=0.01, mob=0.02, g=(1e-4, -2e-4, 3e-4 if dim == 3 else 0.0))
         phi0 = 0.375
         prob["rho_ref"] = 0.5 * (1.0 * (1 + phi0) + 0.25 * (1 - phi0))
         st = W.zero_state(prob)

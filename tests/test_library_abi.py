@@ -112,3 +112,34 @@ def test_axisym_requires_axis_symmetry_bc(G):
 def test_strerror(G):
     for code in (0, -1, -2, -3, -4, -5):
         assert G.gpe_strerror(code) and "unknown" not in G.gpe_strerror(code)
+
+
+def _stability_code(G, prob):
+    """gpe_init_state checks the stability estimates before it touches the
+    workspace: with a NULL workspace it returns GPE_EUNSTABLE or
+    GPE_EWORKSPACE without any device call."""
+    P = G.params_from_problem(prob)
+    h = ctypes.c_void_p()
+    return G.lib().gpe_init_state(ctypes.byref(P), None, 0, None, None, None, ctypes.byref(h))
+
+
+def test_gpu_test_workloads_pass_stability_estimate(G):
+    from tests import test_gpu_parity as T
+
+    probs = [T._case(name)[0] for name in T.CASES]
+    probs += [W.static_drop_2d()[0], W.rising_bubble_3d(nx=256, ny=256, nz=256)[0],
+              W.rayleigh_taylor_2d()[0], W.rising_bubble_3d()[0]]
+    for dim, bc in ((2, (1, 1, 2, 2, 0, 0)), (3, (1, 1, 0, 0, 2, 2))):
+        n = (70, 37, 1) if dim == 2 else (40, 19, 40)
+        probs.append(W.base_problem(dim=dim, n=n, bc=bc, rho_l=1.0, rho_g=0.25, eta_l=0.03,
+                                    eta_g=0.01, sigma=0.01, mob=0.02))
+    for prob in probs:
+        assert _stability_code(G, prob) == G.GPE_EWORKSPACE, prob
+
+
+def test_unstable_time_step_rejected_on_host(G):
+    prob, _ = W.static_drop_2d()
+    prob["mob"] = 0.2
+    assert _stability_code(G, prob) == G.GPE_EUNSTABLE
+    prob["allow_unstable"] = 1
+    assert _stability_code(G, prob) == G.GPE_EWORKSPACE
