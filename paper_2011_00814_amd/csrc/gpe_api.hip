@@ -198,6 +198,11 @@ Consts<T> make_consts(const gpe_params* p, int dim) {
   c.w1 = T(w[1]);
   c.w2 = T(w[2]);
   c.w3 = T(w[3]);
+  c.rho_a = T(0.5 * (p->rho_l + p->rho_g));
+  c.rho_hb = T(0.25 * (p->rho_l - p->rho_g));
+  c.eta_a = T(0.5 * (p->eta_l + p->eta_g));
+  c.eta_b = T(0.5 * (p->eta_l - p->eta_g));
+  c.hsig = T(-0.5 * p->sigma);
   return c;
 }
 

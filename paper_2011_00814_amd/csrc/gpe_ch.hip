@@ -12,6 +12,8 @@
 // m = k+1 it stages phi (plane m+1) and the face velocity sums, then forms
 // mu(m) and the flux vector F(m) = phi u_hat once in LDS rings; the output
 // plane k reads mu and F from planes k-1, k, k+1.
+#include <type_traits>
+
 #include "gpe_plane.hpp"
 
 namespace gpe {
@@ -23,86 +25,74 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
   constexpr int PY = (DIM == 3) ? TY + 4 : 1;
   constexpr int PLANE = PX * PY;
   constexpr int EY = (DIM == 3) ? PX : 0;
-  constexpr int S_PH = 0;           // 3-slot ring: phi planes
-  constexpr int S_SX = 3;           // 1 slot: X face sums of plane m
-  constexpr int S_SY = 4;           // 1 slot: Y face sums of plane m
-  constexpr int S_SZ = 5;           // 2-slot ring: Z face sums
-  constexpr int S_MU = 7;           // 3-slot ring: mu
-  constexpr int S_FX = 10, S_FY = 13, S_FZ = 16;  // 3-slot rings: flux components
-  constexpr int NSLOT = 19;
+  // 3-slot rings (slot of plane m = (m - z0) mod 3): phi, Z face sums, mu,
+  // and the flux components; single slots: X / Y face sums of one plane
+  constexpr int S_PH = 0, S_SZ = 3, S_MU = 6, S_FX = 9, S_FY = 12, S_FZ = 15;
+  constexpr int S_SX = 18, S_SY = 19, NSLOT = 20;
   __shared__ T lds[NSLOT * PLANE];
 
   const Grid& g = A.g;
   const Consts<T>& c = A.c;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
-  const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * TY;
-  const int z0 = (int)blockIdx.z * g.zchunk;
+  int btx, bty, btz;
+  tile_of_block(g, btx, bty, btz);
+  const int x0 = btx * TX, y0 = bty * TY;
+  const int z0 = btz * g.zchunk;
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
+  const T* const L0 = lds + own;
 
   PlaneMap<T, DIM, PX, PY, NT> pm;
   pm.init(g, x0, y0);
 
-  const T* __restrict__ phin = A.phi_in;
-  const T* __restrict__ s_x = A.usum[0];
-  const T* __restrict__ s_y = A.usum[1];
-  const T* __restrict__ s_z = A.usum[2];
-
-  auto slot3 = [](int k) { return (k + 3) % 3; };
-  auto slot2 = [](int k) { return (k + 4) % 2; };
-
-  auto load_phi = [&](int k) {
-    const ZMap<T> z(g, k);
-    T* dst = &lds[(S_PH + slot3(k)) * PLANE];
+  // Staging of the planes an iteration needs (phi of plane k+2, the X/Y face
+  // sums of plane k+1, the Z face sums of plane k+2) is software-pipelined:
+  // fetch() issues the global loads into registers (ghost rules applied),
+  // commit() writes them to LDS one iteration later.  A plane index below -2
+  // marks "nothing to stage".
+  T r_f[pm.NPASS], r_x[pm.NPASS], r_y[pm.NPASS], r_z[pm.NPASS];
+  auto fetch = [&](int kf, int kxy, int kz) {
+    const ZMap<T> zf(g, kf), zxy(g, kxy), zz(g, kz);
+    const T* __restrict__ bf = A.phi_in + zf.zc;
+    const T* __restrict__ bx = A.usum[0] + zxy.zc;
+    const T* __restrict__ by = A.usum[1] + zxy.zc;
+    const T* __restrict__ bz = A.usum[2] + zz.zf;
 #pragma unroll
     for (int p = 0; p < pm.NPASS; ++p) {
-      const int lp = (int)threadIdx.x + p * NT;
-      if (lp >= PLANE) continue;
-      dst[lp] = pm.ok[p] ? phin[z.zc + pm.off_c[p]] : T(0);
-    }
-  };
-  auto load_sz = [&](int k) {
-    const ZMap<T> z(g, k);
-    T* dst = &lds[(S_SZ + slot2(k)) * PLANE];
-#pragma unroll
-    for (int p = 0; p < pm.NPASS; ++p) {
-      const int lp = (int)threadIdx.x + p * NT;
-      if (lp >= PLANE) continue;
-      dst[lp] = pm.ok[p] ? s_z[z.zf + pm.off_c[p]] * (pm.sg_z[p] * z.nrm) : T(0);
-    }
-  };
-  auto load_sxy = [&](int k) {
-    const ZMap<T> z(g, k);
-#pragma unroll
-    for (int p = 0; p < pm.NPASS; ++p) {
-      const int lp = (int)threadIdx.x + p * NT;
-      if (lp >= PLANE) continue;
-      T vx = T(0), vy = T(0);
+      r_f[p] = r_x[p] = r_y[p] = r_z[p] = T(0);
       if (pm.ok[p]) {
-        vx = s_x[z.zc + pm.off_x[p]] * (pm.sg_x[p] * z.tan);
-        if (DIM == 3) vy = s_y[z.zc + pm.off_y[p]] * (pm.sg_y[p] * z.tan);
+        const auto q = pm.pos(g, p);
+        if (kf >= -2) r_f[p] = bf[q.oc];
+        if (kxy >= -2) {
+          r_x[p] = bx[q.ox] * (q.sx * zxy.tan);
+          if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * zxy.tan);
+        }
+        if (kz >= -2) r_z[p] = bz[q.oc] * (q.sz * zz.nrm);
       }
-      lds[S_SX * PLANE + lp] = vx;
-      if (DIM == 3) lds[S_SY * PLANE + lp] = vy;
+    }
+  };
+  auto commit = [&](int sf, int sz, bool do_f, bool do_xy, bool do_z) {
+#pragma unroll
+    for (int p = 0; p < pm.NPASS; ++p) {
+      const int lp = (int)threadIdx.x + p * NT;
+      if (lp >= PLANE) continue;
+      if (do_f) lds[(S_PH + sf) * PLANE + lp] = r_f[p];
+      if (do_xy) {
+        lds[S_SX * PLANE + lp] = r_x[p];
+        if (DIM == 3) lds[S_SY * PLANE + lp] = r_y[p];
+      }
+      if (do_z) lds[(S_SZ + sz) * PLANE + lp] = r_z[p];
     }
   };
 
-  // mu(m) and F(m) = [r] phi u_hat on the region [-1, T] of plane m
-  auto derive = [&](int m) {
-    const T* F0 = &lds[(S_PH + slot3(m)) * PLANE];
-    const T* Fm = &lds[(S_PH + slot3(m - 1)) * PLANE];
-    const T* Fp = &lds[(S_PH + slot3(m + 1)) * PLANE];
-    const T* SX = &lds[S_SX * PLANE];
-    const T* SY = &lds[S_SY * PLANE];
-    const T* SZ0 = &lds[(S_SZ + slot2(m)) * PLANE];
-    const T* SZ1 = &lds[(S_SZ + slot2(m + 1)) * PLANE];
-    T* MU = &lds[(S_MU + slot3(m)) * PLANE];
-    T* FX = &lds[(S_FX + slot3(m)) * PLANE];
-    T* FY = &lds[(S_FY + slot3(m)) * PLANE];
-    T* FZ = &lds[(S_FZ + slot3(m)) * PLANE];
+  // mu(m) and F(m) = [r] phi u_hat on the region [-1, T] of plane m whose
+  // ring slot is SC (planes m-1, m+1 in SM, SP)
+  auto derive = [&](int m, auto sc) {
+    constexpr int SC = decltype(sc)::value;
+    constexpr int SM = (SC + 2) % 3, SP = (SC + 1) % 3;
     T rp = T(1), rm = T(1), rnode = T(1);
     if (AXI) {
       // A ghost plane beyond the axis or the outer wall mirrors an in-domain
@@ -121,149 +111,190 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
     for (int e = (int)threadIdx.x; e < EN; e += NT) {
       const int ex = e % EXN, ey = e / EXN;
       const int q = ((DIM == 3) ? (ey + 1) * PX : 0) + ex + 1;
-      const T f = F0[q];
+      T* b = lds + q;
+      const T* F0 = b + (S_PH + SC) * PLANE;
+      const T* Fm = b + (S_PH + SM) * PLANE;
+      const T* Fp = b + (S_PH + SP) * PLANE;
+      const T f = F0[0];
       T lap;
       if (DIM == 2) {
-        const T s1 = (F0[q + 1] - f) + (F0[q - 1] - f) + rp * (Fp[q] - f) + rm * (Fm[q] - f);
-        const T s2 = rp * ((Fp[q + 1] - f) + (Fp[q - 1] - f)) + rm * ((Fm[q + 1] - f) + (Fm[q - 1] - f));
+        const T s1 = ((F0[1] - f) + (F0[-1] - f)) + (rp * (Fp[0] - f) + rm * (Fm[0] - f));
+        const T s2 = rp * ((Fp[1] - f) + (Fp[-1] - f)) + rm * ((Fm[1] - f) + (Fm[-1] - f));
         lap = c.w1 * s1 + c.w2 * s2;
       } else {
-        const T s1 = ((F0[q + 1] - f) + (F0[q - 1] - f)) + ((F0[q + EY] - f) + (F0[q - EY] - f)) +
-                     ((Fp[q] - f) + (Fm[q] - f));
+        const T s1 = ((F0[1] - f) + (F0[-1] - f)) + ((F0[EY] - f) + (F0[-EY] - f)) +
+                     ((Fp[0] - f) + (Fm[0] - f));
         lap = c.w1 * s1;
         if (c.w2 != T(0)) {
-          const T s2 = ((F0[q + 1 + EY] - f) + (F0[q + 1 - EY] - f) + (F0[q - 1 + EY] - f) +
-                        (F0[q - 1 - EY] - f)) +
-                       ((Fp[q + 1] - f) + (Fp[q - 1] - f) + (Fp[q + EY] - f) + (Fp[q - EY] - f)) +
-                       ((Fm[q + 1] - f) + (Fm[q - 1] - f) + (Fm[q + EY] - f) + (Fm[q - EY] - f));
+          const T s2 = ((F0[1 + EY] - f) + (F0[1 - EY] - f) + (F0[-1 + EY] - f) + (F0[-1 - EY] - f)) +
+                       ((Fp[1] - f) + (Fp[-1] - f) + (Fp[EY] - f) + (Fp[-EY] - f)) +
+                       ((Fm[1] - f) + (Fm[-1] - f) + (Fm[EY] - f) + (Fm[-EY] - f));
           lap += c.w2 * s2;
         }
         if (c.w3 != T(0)) {
-          const T s3 = ((Fp[q + 1 + EY] - f) + (Fp[q + 1 - EY] - f) + (Fp[q - 1 + EY] - f) +
-                        (Fp[q - 1 - EY] - f)) +
-                       ((Fm[q + 1 + EY] - f) + (Fm[q + 1 - EY] - f) + (Fm[q - 1 + EY] - f) +
-                        (Fm[q - 1 - EY] - f));
+          const T s3 = ((Fp[1 + EY] - f) + (Fp[1 - EY] - f) + (Fp[-1 + EY] - f) + (Fp[-1 - EY] - f)) +
+                       ((Fm[1 + EY] - f) + (Fm[1 - EY] - f) + (Fm[-1 + EY] - f) + (Fm[-1 - EY] - f));
           lap += c.w3 * s3;
         }
       }
-      MU[q] = c.a4 * f * (f * f - T(1)) - c.kappa6 * lap;
+      b[(S_MU + SC) * PLANE] = c.a4 * f * (f * f - T(1)) - c.kappa6 * lap;
+      // centre velocity = 1/4 of the sums over its two faces; the factor 1/4
+      // is applied in the flux divergence
       const T pr = AXI ? f * rnode : f;
-      FX[q] = pr * (T(0.25) * (SX[q] + SX[q + 1]));
-      if (DIM == 3) FY[q] = pr * (T(0.25) * (SY[q] + SY[q + EY]));
-      FZ[q] = pr * (T(0.25) * (SZ0[q] + SZ1[q]));
+      const T* SX = b + S_SX * PLANE;
+      const T* SY = b + S_SY * PLANE;
+      b[(S_FX + SC) * PLANE] = pr * (SX[0] + SX[1]);
+      if (DIM == 3) b[(S_FY + SC) * PLANE] = pr * (SY[0] + SY[EY]);
+      b[(S_FZ + SC) * PLANE] = pr * (b[(S_SZ + SC) * PLANE] + b[(S_SZ + SP) * PLANE]);
     }
   };
 
-  // -------- warm-up -------------------------------------------------------
-  load_phi(z0 - 2);
-  load_phi(z0 - 1);
-  load_sz(z0 - 1);
-  // iterations k = z0-2, z0-1 only stage and derive planes z0-1, z0
-  for (int k = z0 - 2; k < z1; ++k) {
-    load_phi(k + 2);
-    load_sxy(k + 1);
-    load_sz(k + 2);
-    __syncthreads();
-    derive(k + 1);
-    __syncthreads();
-    if (k >= z0 && active) {
-      const int sm = slot3(k - 1), s0 = slot3(k), s1 = slot3(k + 1);
-      const T* M0 = &lds[(S_MU + s0) * PLANE + own];
-      const T* Mm = &lds[(S_MU + sm) * PLANE + own];
-      const T* Mp = &lds[(S_MU + s1) * PLANE + own];
-      const T* X0 = &lds[(S_FX + s0) * PLANE + own];
-      const T* Xm = &lds[(S_FX + sm) * PLANE + own];
-      const T* Xp = &lds[(S_FX + s1) * PLANE + own];
-      const T* Y0 = &lds[(S_FY + s0) * PLANE + own];
-      const T* Ym = &lds[(S_FY + sm) * PLANE + own];
-      const T* Yp = &lds[(S_FY + s1) * PLANE + own];
-      const T* Z0 = &lds[(S_FZ + s0) * PLANE + own];
-      const T* Zm = &lds[(S_FZ + sm) * PLANE + own];
-      const T* Zp = &lds[(S_FZ + s1) * PLANE + own];
-      T rp = T(1), rm = T(1), inv_r = T(1);
-      if (AXI) {
-        const T rk = T(k) + T(0.5);
-        rp = (rk + T(0.5)) / rk;
-        rm = (rk - T(0.5)) / rk;
-        inv_r = T(1) / rk;
-      }
-      const T mc = M0[0];
-      T lap, flux;
-      if (DIM == 2) {
-        const T s1 = (M0[1] - mc) + (M0[-1] - mc) + rp * (Mp[0] - mc) + rm * (Mm[0] - mc);
-        const T s2 = rp * ((Mp[1] - mc) + (Mp[-1] - mc)) + rm * ((Mm[1] - mc) + (Mm[-1] - mc));
-        lap = c.w1 * s1 + c.w2 * s2;
-        // D2Q9 in the (X, Z) plane: axis links and the four diagonals
-        const T f1 = (X0[1] - X0[-1]) + (Zp[0] - Zm[0]);
-        const T f2 = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
-        flux = (c.w1 * f1 + c.w2 * f2) * inv_r;
-      } else {
-        const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + ((M0[EY] - mc) + (M0[-EY] - mc)) +
-                     ((Mp[0] - mc) + (Mm[0] - mc));
-        lap = c.w1 * s1;
-        flux = c.w1 * ((X0[1] - X0[-1]) + (Y0[EY] - Y0[-EY]) + (Zp[0] - Zm[0]));
-        if (c.w2 != T(0)) {
-          const T s2 = ((M0[1 + EY] - mc) + (M0[1 - EY] - mc) + (M0[-1 + EY] - mc) + (M0[-1 - EY] - mc)) +
-                       ((Mp[1] - mc) + (Mp[-1] - mc) + (Mp[EY] - mc) + (Mp[-EY] - mc)) +
-                       ((Mm[1] - mc) + (Mm[-1] - mc) + (Mm[EY] - mc) + (Mm[-EY] - mc));
-          lap += c.w2 * s2;
-          // edges: XY in plane k, XZ and YZ in planes k +- 1
-          const T exy = ((X0[1 + EY] + X0[1 - EY]) - (X0[-1 + EY] + X0[-1 - EY])) +
-                        ((Y0[1 + EY] + Y0[-1 + EY]) - (Y0[1 - EY] + Y0[-1 - EY]));
-          const T exz = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
-          const T eyz = ((Yp[EY] - Yp[-EY]) + (Ym[EY] - Ym[-EY])) + ((Zp[EY] + Zp[-EY]) - (Zm[EY] + Zm[-EY]));
-          flux += c.w2 * (exy + (exz + eyz));
-        }
-        if (c.w3 != T(0)) {
-          const T s3 = ((Mp[1 + EY] - mc) + (Mp[1 - EY] - mc) + (Mp[-1 + EY] - mc) + (Mp[-1 - EY] - mc)) +
-                       ((Mm[1 + EY] - mc) + (Mm[1 - EY] - mc) + (Mm[-1 + EY] - mc) + (Mm[-1 - EY] - mc));
-          lap += c.w3 * s3;
-          // corners (sx, sy, sz): sx F_X + sy F_Y + sz F_Z at planes k +- 1
-          auto corner = [&](const T* X, const T* Y) {
-            return ((X[1 + EY] + X[1 - EY]) - (X[-1 + EY] + X[-1 - EY])) +
-                   ((Y[1 + EY] + Y[-1 + EY]) - (Y[1 - EY] + Y[-1 - EY]));
-          };
-          const T zs = ((Zp[1 + EY] + Zp[1 - EY]) + (Zp[-1 + EY] + Zp[-1 - EY])) -
-                       ((Zm[1 + EY] + Zm[1 - EY]) + (Zm[-1 + EY] + Zm[-1 - EY]));
-          flux += c.w3 * ((corner(Xp, Yp) + corner(Xm, Ym)) + zs);
-        }
-      }
-      const T L = T(-3) * flux + T(6) * c.mob * lap;
+  // pointwise stage inputs (phi* and the RK4 running sum) at the thread's
+  // own cell, loaded one plane ahead of their use
+  constexpr bool NEED_PHIS = STAGE == CH_RK2_2 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3;
+  constexpr bool NEED_ACC = STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
+  T phis_cur = T(0), acc_cur = T(0), phis_next = T(0), acc_next = T(0);
+  auto fetch_pt = [&](int k, T& ps, T& ac) {
+    if (active && k >= z0 && k < z1) {
       const size_t ci = ((size_t)k * ny + j) * nx + i;
-      const T dt = c.dt;
-      const T phc = lds[(S_PH + s0) * PLANE + own];
-      if (STAGE == CH_RK2_1) {
-        A.out[ci] = phc + dt * L;
-      } else if (STAGE == CH_RK2_2) {
-        const T ps = A.phis[ci];
-        A.out[ci] = ps + T(0.5) * ((phc - ps) + dt * L);
-      } else if (STAGE == CH_RK4_1) {
-        const T kk = dt * L;
-        A.out[ci] = phc + T(0.5) * kk;
-        A.acc[ci] = phc + kk * T(1.0 / 6.0);
-      } else if (STAGE == CH_RK4_2) {
-        const T kk = dt * L;
-        A.out[ci] = A.phis[ci] + T(0.5) * kk;
-        A.acc[ci] = A.acc[ci] + kk * T(1.0 / 3.0);
-      } else if (STAGE == CH_RK4_3) {
-        const T kk = dt * L;
-        A.out[ci] = A.phis[ci] + kk;
-        A.acc[ci] = A.acc[ci] + kk * T(1.0 / 3.0);
-      } else {
-        const T kk = dt * L;
-        A.out[ci] = A.acc[ci] + kk * T(1.0 / 6.0);
+      if (NEED_PHIS) ps = A.phis[ci];
+      if (NEED_ACC) ac = A.acc[ci];
+    }
+  };
+
+  // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP)
+  auto output = [&](int k, auto s0) {
+    constexpr int S0 = decltype(s0)::value;
+    constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
+    const T* M0 = L0 + (S_MU + S0) * PLANE;
+    const T* Mm = L0 + (S_MU + SM) * PLANE;
+    const T* Mp = L0 + (S_MU + SP) * PLANE;
+    const T* X0 = L0 + (S_FX + S0) * PLANE;
+    const T* Xm = L0 + (S_FX + SM) * PLANE;
+    const T* Xp = L0 + (S_FX + SP) * PLANE;
+    const T* Y0 = L0 + (S_FY + S0) * PLANE;
+    const T* Ym = L0 + (S_FY + SM) * PLANE;
+    const T* Yp = L0 + (S_FY + SP) * PLANE;
+    const T* Z0 = L0 + (S_FZ + S0) * PLANE;
+    const T* Zm = L0 + (S_FZ + SM) * PLANE;
+    const T* Zp = L0 + (S_FZ + SP) * PLANE;
+    T rp = T(1), rm = T(1), inv_r = T(1);
+    if (AXI) {
+      const T rk = T(k) + T(0.5);
+      inv_r = T(1) / rk;
+      rp = (rk + T(0.5)) * inv_r;
+      rm = (rk - T(0.5)) * inv_r;
+    }
+    const T mc = M0[0];
+    T lap, flux;
+    if (DIM == 2) {
+      const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + (rp * (Mp[0] - mc) + rm * (Mm[0] - mc));
+      const T s2 = rp * ((Mp[1] - mc) + (Mp[-1] - mc)) + rm * ((Mm[1] - mc) + (Mm[-1] - mc));
+      lap = c.w1 * s1 + c.w2 * s2;
+      // D2Q9 in the (X, Z) plane: axis links and the four diagonals
+      const T f1 = (X0[1] - X0[-1]) + (Zp[0] - Zm[0]);
+      const T f2 = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
+      flux = (c.w1 * f1 + c.w2 * f2) * inv_r;
+    } else {
+      const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + ((M0[EY] - mc) + (M0[-EY] - mc)) +
+                   ((Mp[0] - mc) + (Mm[0] - mc));
+      lap = c.w1 * s1;
+      flux = c.w1 * ((X0[1] - X0[-1]) + (Y0[EY] - Y0[-EY]) + (Zp[0] - Zm[0]));
+      if (c.w2 != T(0)) {
+        const T s2 = ((M0[1 + EY] - mc) + (M0[1 - EY] - mc) + (M0[-1 + EY] - mc) + (M0[-1 - EY] - mc)) +
+                     ((Mp[1] - mc) + (Mp[-1] - mc) + (Mp[EY] - mc) + (Mp[-EY] - mc)) +
+                     ((Mm[1] - mc) + (Mm[-1] - mc) + (Mm[EY] - mc) + (Mm[-EY] - mc));
+        lap += c.w2 * s2;
+        // edges: XY in plane k, XZ and YZ in planes k +- 1
+        const T exy = ((X0[1 + EY] + X0[1 - EY]) - (X0[-1 + EY] + X0[-1 - EY])) +
+                      ((Y0[1 + EY] + Y0[-1 + EY]) - (Y0[1 - EY] + Y0[-1 - EY]));
+        const T exz = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
+        const T eyz = ((Yp[EY] - Yp[-EY]) + (Ym[EY] - Ym[-EY])) + ((Zp[EY] + Zp[-EY]) - (Zm[EY] + Zm[-EY]));
+        flux += c.w2 * (exy + (exz + eyz));
+      }
+      if (c.w3 != T(0)) {
+        const T s3 = ((Mp[1 + EY] - mc) + (Mp[1 - EY] - mc) + (Mp[-1 + EY] - mc) + (Mp[-1 - EY] - mc)) +
+                     ((Mm[1 + EY] - mc) + (Mm[1 - EY] - mc) + (Mm[-1 + EY] - mc) + (Mm[-1 - EY] - mc));
+        lap += c.w3 * s3;
+        // corners (sx, sy, sz): sx F_X + sy F_Y + sz F_Z at planes k +- 1
+        auto corner = [&](const T* X, const T* Y) {
+          return ((X[1 + EY] + X[1 - EY]) - (X[-1 + EY] + X[-1 - EY])) +
+                 ((Y[1 + EY] + Y[-1 + EY]) - (Y[1 - EY] + Y[-1 - EY]));
+        };
+        const T zs = ((Zp[1 + EY] + Zp[1 - EY]) + (Zp[-1 + EY] + Zp[-1 - EY])) -
+                     ((Zm[1 + EY] + Zm[1 - EY]) + (Zm[-1 + EY] + Zm[-1 - EY]));
+        flux += c.w3 * ((corner(Xp, Yp) + corner(Xm, Ym)) + zs);
       }
     }
+    // L = -3 sum_i w_i e_i . F(x + e_i) + 6 M sum_i w_i (mu_i - mu); the
+    // stored fluxes carry 4x the centre velocity
+    const T L = T(-0.75) * flux + T(6) * c.mob * lap;
+    const size_t ci = ((size_t)k * ny + j) * nx + i;
+    const T dt = c.dt;
+    const T phc = L0[(S_PH + S0) * PLANE];
+    const T ps = phis_cur, ac = acc_cur;
+    if (STAGE == CH_RK2_1) {
+      A.out[ci] = fma(dt, L, phc);
+    } else if (STAGE == CH_RK2_2) {
+      A.out[ci] = ps + T(0.5) * ((phc - ps) + dt * L);
+    } else if (STAGE == CH_RK4_1) {
+      const T kk = dt * L;
+      A.out[ci] = fma(T(0.5), kk, phc);
+      A.acc[ci] = fma(kk, T(1.0 / 6.0), phc);
+    } else if (STAGE == CH_RK4_2) {
+      const T kk = dt * L;
+      A.out[ci] = fma(T(0.5), kk, ps);
+      A.acc[ci] = fma(kk, T(1.0 / 3.0), ac);
+    } else if (STAGE == CH_RK4_3) {
+      const T kk = dt * L;
+      A.out[ci] = ps + kk;
+      A.acc[ci] = fma(kk, T(1.0 / 3.0), ac);
+    } else {
+      const T kk = dt * L;
+      A.out[ci] = fma(kk, T(1.0 / 6.0), ac);
+    }
+  };
+
+  // one iteration: stage phi(k+2), the X/Y sums of plane k+1 and the Z sums
+  // of plane k+2, derive mu and F of plane k+1, write plane k (k >= z0)
+  auto iter = [&](int k, auto sk) {
+    constexpr int SK = decltype(sk)::value;  // slot of plane k
+    constexpr int S1 = (SK + 1) % 3, S2 = (SK + 2) % 3;
+    commit(S2, S2, true, true, true);
+    if (k + 1 < z1) fetch(k + 3, k + 2, k + 3);  // in flight during this plane's work
+    fetch_pt(k + 1, phis_next, acc_next);
     __syncthreads();
+    derive(k + 1, std::integral_constant<int, S1>{});
+    __syncthreads();
+    if (k >= z0 && active) output(k, std::integral_constant<int, SK>{});
+    phis_cur = phis_next;
+    acc_cur = acc_next;
+    __syncthreads();
+  };
+
+  // -------- warm-up: phi(z0-2), phi(z0-1) and the Z sums of plane z0-1 ----
+  fetch(z0 - 2, -3, z0 - 1);
+  commit(1, 2, true, false, true);
+  fetch(z0 - 1, -3, -3);
+  commit(2, 0, true, false, false);
+  fetch(z0, z0 - 1, z0);
+  // iterations k = z0-2, z0-1 only stage and derive planes z0-1, z0
+  for (int k = z0 - 2; k < z1; k += 3) {
+    iter(k, std::integral_constant<int, 1>{});
+    if (k + 1 < z1) iter(k + 1, std::integral_constant<int, 2>{});
+    if (k + 2 < z1) iter(k + 2, std::integral_constant<int, 0>{});
   }
 }
 
 template <typename T, int DIM, bool AXI, int STAGE>
 static hipError_t launch_ch_t(const ChArgs<T>& a, hipStream_t s) {
   constexpr int TX = ChTile<DIM>::TX, TY = ChTile<DIM>::TY;
-  dim3 grid((a.g.n[0] + TX - 1) / TX, (a.g.n[1] + TY - 1) / TY,
-            (a.g.n[2] + a.g.zchunk - 1) / a.g.zchunk);
-  hipLaunchKernelGGL((ch_stage_kernel<T, DIM, AXI, STAGE, TX, TY>), grid, dim3(TX * TY), 0, s, a);
+  ChArgs<T> b = a;
+  b.g.nb[0] = (a.g.n[0] + TX - 1) / TX;
+  b.g.nb[1] = (a.g.n[1] + TY - 1) / TY;
+  b.g.nb[2] = (a.g.n[2] + a.g.zchunk - 1) / a.g.zchunk;
+  const unsigned nblk = (unsigned)(b.g.nb[0] * b.g.nb[1] * b.g.nb[2]);
+  hipLaunchKernelGGL((ch_stage_kernel<T, DIM, AXI, STAGE, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, b);
   return hipGetLastError();
 }
 

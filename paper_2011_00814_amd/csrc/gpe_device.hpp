@@ -20,7 +20,23 @@ struct Grid {
   int n[3];    // cells along X, Y, Z (n[1] = 1 in 2-D)
   int bc[6];   // X-lo, X-hi, Y-lo, Y-hi, Z-lo, Z-hi
   int zchunk;  // output planes per work-group along Z
+  int nb[3];   // work-group tiles along X, Y and Z chunks (set by the launcher)
 };
+
+// Work-groups of a 1-D launch are dispatched round-robin over the 8 XCDs
+// (each with its own L2).  Give every XCD a contiguous run of the tile index
+// (X fastest, then Y, then Z chunk) so that tiles sharing halo rows share an
+// L2: tile = xcd * (nb / 8) + min(xcd, nb % 8) + (block / 8).
+__device__ __forceinline__ void tile_of_block(const Grid& g, int& tx, int& ty, int& tz) {
+  const int nb = g.nb[0] * g.nb[1] * g.nb[2];
+  const int b = (int)blockIdx.x;
+  const int xcd = b % 8, local = b / 8;
+  const int per = nb / 8, rem = nb % 8;
+  const int L = xcd * per + min(xcd, rem) + local;
+  tx = L % g.nb[0];
+  ty = (L / g.nb[0]) % g.nb[1];
+  tz = L / (g.nb[0] * g.nb[1]);
+}
 
 // Constants in the working precision.
 template <typename T>
@@ -33,6 +49,9 @@ struct Consts {
   T rho_ref;
   T g[3];    // body force, internal axis order
   T w1, w2, w3;  // lattice weights of links with 1, 2, 3 non-zero components
+  // mixture laws as affine maps of the clamped phase field f:
+  // rho = rho_a + 2 rho_hb f, eta = eta_a + eta_b f; hsig = -sigma / 2
+  T rho_a, rho_hb, eta_a, eta_b, hsig;
 };
 
 template <typename T>
@@ -110,16 +129,17 @@ __device__ __forceinline__ T clamp1(T x) {
   return fmin(fmax(x, T(-1)), T(1));
 }
 
+// rho(phi) = [rho_L (1 + f) + rho_G (1 - f)] / 2 and likewise eta (f = phi
+// clamped to [-1, 1]), evaluated as affine maps with host-precomputed
+// coefficients.
 template <typename T>
 __device__ __forceinline__ T rho_of(const Consts<T>& c, T phi) {
-  T f = clamp1(phi);
-  return T(0.5) * (c.rho_l * (T(1) + f) + c.rho_g * (T(1) - f));
+  return fma(T(2) * c.rho_hb, clamp1(phi), c.rho_a);
 }
 
 template <typename T>
 __device__ __forceinline__ T eta_of(const Consts<T>& c, T phi) {
-  T f = clamp1(phi);
-  return T(0.5) * (c.eta_l * (T(1) + f) + c.eta_g * (T(1) - f));
+  return fma(c.eta_b, clamp1(phi), c.eta_a);
 }
 
 // Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.

@@ -11,12 +11,27 @@
 // its cell, applies the Shu-Osher combination of the stage and writes the
 // result.  Stage 3 updates time level n in place and also writes the face
 // velocity sums u^n + u^{n+1} used for the centre velocity of the CH step.
+//
+// The plane loop is unrolled by three with ring slots counted from the tile
+// start, so every LDS address is a compile-time offset from the thread's own
+// position.  The transverse pressure average of the in-plane faces is
+// separable: its per-plane partial sums are carried in registers.  In FP32
+// the next plane's global loads are issued before the current plane's
+// stencil work (software pipelining).
+#include <type_traits>
+
 #include "gpe_plane.hpp"
 
 namespace gpe {
 
+// Occupancy target: 4 waves per SIMD in FP32 (<= 128 VGPRs); the FP64
+// kernel is left to the compiler's register allocation.
+template <typename T>
+struct FlowOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 1; };
+
 template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
+__global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowArgs<T> A) {
+  constexpr bool PREFETCH = sizeof(T) == 4;
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 3;                  // in-plane X range [-2, TX]
   constexpr int PY = (DIM == 3) ? TY + 3 : 1;  // in-plane Y range [-2, TY]
@@ -31,67 +46,75 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
   const Consts<T>& c = A.c;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
-  const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * TY;
-  const int z0 = (int)blockIdx.z * g.zchunk;
+  int btx, bty, btz;
+  tile_of_block(g, btx, bty, btz);
+  const int x0 = btx * TX, y0 = bty * TY;
+  const int z0 = btz * g.zchunk;
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
+  T* const L0 = lds + own;  // LDS base of the thread's own column
 
   PlaneMap<T, DIM, PX, PY, NT> pm;
   pm.init(g, x0, y0);
 
-  const T* __restrict__ sp = A.src[0];
-  const T* __restrict__ su = A.src[1];
-  const T* __restrict__ sv = A.src[2];
-  const T* __restrict__ sw = A.src[3];
-  const T* __restrict__ phi = A.phi;
-
-  auto slot = [](int k) { return (k + 3) % 3; };
-
-  // Stage plane k (ghost rules applied) into ring slot s.
-  auto load_plane = [&](int k, int s) {
+  // ---- plane staging: fetch() issues the global loads of a plane (ghost
+  // rules applied) into registers, commit() writes them and the derived eta
+  // and nu into a ring slot
+  T r_p[pm.NPASS], r_x[pm.NPASS], r_y[pm.NPASS], r_z[pm.NPASS], r_f[pm.NPASS];
+  auto fetch = [&](int k) {
     const ZMap<T> z(g, k);
+    const T* __restrict__ bp = A.src[0] + z.zc;
+    const T* __restrict__ bx = A.src[1] + z.zc;
+    const T* __restrict__ by = A.src[2] + z.zc;
+    const T* __restrict__ bz = A.src[3] + z.zf;
+    const T* __restrict__ bf = A.phi + z.zc;
+#pragma unroll
+    for (int p = 0; p < pm.NPASS; ++p) {
+      r_p[p] = r_x[p] = r_y[p] = r_z[p] = r_f[p] = T(0);
+      if (pm.ok[p]) {
+        const auto q = pm.pos(g, p);
+        r_p[p] = bp[q.oc];
+        r_x[p] = bx[q.ox] * (q.sx * z.tan);
+        if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * z.tan);
+        r_z[p] = bz[q.oc] * (q.sz * z.nrm);
+        r_f[p] = bf[q.oc];
+      }
+    }
+  };
+  auto commit = [&](int s) {
 #pragma unroll
     for (int p = 0; p < pm.NPASS; ++p) {
       const int lp = (int)threadIdx.x + p * NT;
       if (lp >= PLANE) continue;
-      T vp = T(0), vx = T(0), vy = T(0), vz = T(0), ph = T(0);
-      if (pm.ok[p]) {
-        vp = sp[z.zc + pm.off_c[p]];
-        vx = su[z.zc + pm.off_x[p]] * (pm.sg_x[p] * z.tan);
-        if (DIM == 3) vy = sv[z.zc + pm.off_y[p]] * (pm.sg_y[p] * z.tan);
-        vz = sw[z.zf + pm.off_c[p]] * (pm.sg_z[p] * z.nrm);
-        ph = phi[z.zc + pm.off_c[p]];
-      }
+      const T ph = r_f[p];
       const T eta = eta_of(c, ph);
-      const T rho = rho_of(c, ph);
-      lds[(S_P + s) * PLANE + lp] = vp;
-      lds[(S_UX + s) * PLANE + lp] = vx;
-      if (DIM == 3) lds[(S_UY + s) * PLANE + lp] = vy;
-      lds[(S_UZ + s) * PLANE + lp] = vz;
+      lds[(S_P + s) * PLANE + lp] = r_p[p];
+      lds[(S_UX + s) * PLANE + lp] = r_x[p];
+      if (DIM == 3) lds[(S_UY + s) * PLANE + lp] = r_y[p];
+      lds[(S_UZ + s) * PLANE + lp] = r_z[p];
       lds[(S_PH + s) * PLANE + lp] = ph;
       lds[(S_ET + s) * PLANE + lp] = eta;
-      lds[(S_NU + s) * PLANE + lp] = eta * recip(rho);
+      lds[(S_NU + s) * PLANE + lp] = eta * recip(rho_of(c, ph));
     }
   };
 
-  // Chemical potential at LDS position q of plane k (phi ring planes k-1..k+1):
-  // mu = 4 a phi (phi^2 - 1) - 6 kappa sum_i w_i (phi_i - phi_c)  (Sec. 2, Sec. 3)
-  auto mu_at = [&](int k, int q) -> T {
-    const T* F0 = &lds[(S_PH + slot(k)) * PLANE + q];
-    const T* Fm = &lds[(S_PH + slot(k - 1)) * PLANE + q];
-    const T* Fp = &lds[(S_PH + slot(k + 1)) * PLANE + q];
+  // ---- chemical potential at an LDS position of plane k, given its phi
+  // planes k, k-1, k+1 (Sec. 2, Sec. 3 isotropic Laplacian):
+  // mu = 4 a phi (phi^2 - 1) - 6 kappa sum_i w_i (phi_i - phi_c)
+  auto mu_at = [&](int k, const T* F0, const T* Fm, const T* Fp) -> T {
     const T f = F0[0];
     T rp = T(1), rm = T(1);
     if (AXI) {  // Z is radial: weight every link by its mid-point radius / r_k
       const T rk = T(k) + T(0.5);
-      rp = (rk + T(0.5)) / rk;
-      rm = (rk - T(0.5)) / rk;
+      const T ir = T(1) / rk;
+      rp = (rk + T(0.5)) * ir;
+      rm = (rk - T(0.5)) * ir;
     }
     T lap;
     if (DIM == 2) {
-      const T s1 = (F0[1] - f) + (F0[-1] - f) + rp * (Fp[0] - f) + rm * (Fm[0] - f);
+      const T s1 = ((F0[1] - f) + (F0[-1] - f)) + (rp * (Fp[0] - f) + rm * (Fm[0] - f));
       const T s2 = rp * ((Fp[1] - f) + (Fp[-1] - f)) + rm * ((Fm[1] - f) + (Fm[-1] - f));
       lap = c.w1 * s1 + c.w2 * s2;
     } else {
@@ -113,17 +136,11 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
     return c.a4 * f * (f * f - T(1)) - c.kappa6 * lap;
   };
 
-  // Velocity divergence at LDS position q of plane k (Sec. 3, div stencil);
-  // axisymmetric: (1/r) d(r u_r)/dr with face radii k and k+1.
-  auto div_at = [&](int k, int q) -> T {
-    const T* UX = &lds[(S_UX + slot(k)) * PLANE + q];
-    const T* UZ0 = &lds[(S_UZ + slot(k)) * PLANE + q];
-    const T* UZp = &lds[(S_UZ + slot(k + 1)) * PLANE + q];
+  // ---- velocity divergence at an LDS position of plane k (Sec. 3 div
+  // stencil); axisymmetric: (1/r) d(r u_r)/dr with face radii k and k+1
+  auto div_at = [&](int k, const T* UX, const T* UY, const T* UZ0, const T* UZp) -> T {
     T d = UX[1] - UX[0];
-    if (DIM == 3) {
-      const T* UY = &lds[(S_UY + slot(k)) * PLANE + q];
-      d += UY[EY] - UY[0];
-    }
+    if (DIM == 3) d += UY[EY] - UY[0];
     if (AXI) {
       const T rk = T(k) + T(0.5);
       d += ((T(k) + T(1)) * UZp[0] - T(k) * UZ0[0]) / rk;
@@ -133,17 +150,59 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
     return d;
   };
 
-  // -------- warm-up: planes z0-2 .. z0 -------------------------------------
-  load_plane(z0 - 2, slot(z0 - 2));
-  load_plane(z0 - 1, slot(z0 - 1));
-  load_plane(z0, slot(z0));
-  __syncthreads();
-  T mu_prev = mu_at(z0 - 1, own);
-  T dv_prev = div_at(z0 - 1, own);
-  __syncthreads();
+  // ---- separable part of the transverse pressure average of an in-plane
+  // face (normal offset ea, other in-plane axis eb) on one plane,
+  // difference-first: 4 D_0 + D_{+b} + D_{-b} with D = p - p_{-a}
+  auto prow = [&](const T* P, int ea, int eb) -> T {
+    if (DIM == 2) return P[0] - P[-ea];
+    return T(4) * (P[0] - P[-ea]) + ((P[eb] - P[eb - ea]) + (P[-eb] - P[-eb - ea]));
+  };
 
-  for (int k = z0; k < z1; ++k) {
-    load_plane(k + 1, slot(k + 1));
+  // -------- warm-up: planes z0-2, z0-1, z0 into slots 1, 2, 0 -------------
+  // (the ring slot of plane k is (k - z0) mod 3)
+  fetch(z0 - 2);
+  commit(1);
+  fetch(z0 - 1);
+  commit(2);
+  fetch(z0);
+  commit(0);
+  __syncthreads();
+  T mu_prev = mu_at(z0 - 1, L0 + (S_PH + 2) * PLANE, L0 + (S_PH + 1) * PLANE, L0 + (S_PH + 0) * PLANE);
+  T dv_prev = div_at(z0 - 1, L0 + (S_UX + 2) * PLANE, L0 + (S_UY + 2) * PLANE, L0 + (S_UZ + 2) * PLANE,
+                     L0 + (S_UZ + 0) * PLANE);
+  T gx_m = prow(L0 + (S_P + 2) * PLANE, 1, EY), gx_0 = prow(L0 + (S_P + 0) * PLANE, 1, EY);
+  T gy_m = T(0), gy_0 = T(0);
+  if (DIM == 3) {
+    gy_m = prow(L0 + (S_P + 2) * PLANE, EY, 1);
+    gy_0 = prow(L0 + (S_P + 0) * PLANE, EY, 1);
+  }
+  if (PREFETCH) fetch(z0 + 1);
+
+  // time level n at the thread's own cell (stages 2 and 3).  FP64 loads it
+  // at the top of the plane's step so that its latency overlaps the mu / div
+  // phase; FP32 (register-capped for occupancy) loads it where it is used.
+  constexpr bool QN_EARLY = sizeof(T) == 8;
+  auto fetch_qn = [&](int k, T* dst) {
+    if (STAGE >= 2 && active) {
+      const size_t ci = ((size_t)k * ny + j) * nx + i;
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        if (DIM == 3 || f != 2) dst[f] = A.qn[f][ci];
+    }
+  };
+
+  const T dt = c.dt;
+
+  // one output plane k; planes k, k-1, k+1 sit in ring slots S0, SM, SP
+  auto step = [&](auto slots, int k) {
+    constexpr int S0 = decltype(slots)::value;
+    constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
+    __syncthreads();  // readers of slot SP (plane k-2) are done
+    if (!PREFETCH) fetch(k + 1);
+    commit(SP);
+    if (PREFETCH && k + 1 < z1) fetch(k + 2);  // in flight during this plane's work
+    T qn_cur[4] = {T(0), T(0), T(0), T(0)};
+    if (QN_EARLY) fetch_qn(k, qn_cur);
     __syncthreads();
 
     // mu and div u of plane k on [-1, T-1] (LDS positions 1 .. T+1)
@@ -153,108 +212,107 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
       for (int e = (int)threadIdx.x; e < EN; e += NT) {
         const int ex = e % EX_N, ey = e / EX_N;
         const int q = ((DIM == 3) ? (ey + 1) * PX : 0) + ex + 1;
-        lds[S_MU * PLANE + q] = mu_at(k, q);
-        lds[S_DV * PLANE + q] = div_at(k, q);
+        T* b = lds + q;
+        b[S_MU * PLANE] = mu_at(k, b + (S_PH + S0) * PLANE, b + (S_PH + SM) * PLANE, b + (S_PH + SP) * PLANE);
+        b[S_DV * PLANE] = div_at(k, b + (S_UX + S0) * PLANE, b + (S_UY + S0) * PLANE,
+                                 b + (S_UZ + S0) * PLANE, b + (S_UZ + SP) * PLANE);
       }
     }
+    // pressure-average partial sums of plane k+1 (own column)
+    const T gx_p = prow(L0 + (S_P + SP) * PLANE, 1, EY);
+    T gy_p = T(0);
+    if (DIM == 3) gy_p = prow(L0 + (S_P + SP) * PLANE, EY, 1);
     __syncthreads();
 
     if (active) {
-      const int sm = slot(k - 1), s0 = slot(k), s1 = slot(k + 1);
-      const T* P0 = &lds[(S_P + s0) * PLANE + own];
-      const T* Pm = &lds[(S_P + sm) * PLANE + own];
-      const T* Pp = &lds[(S_P + s1) * PLANE + own];
-      const T* UX0 = &lds[(S_UX + s0) * PLANE + own];
-      const T* UXm = &lds[(S_UX + sm) * PLANE + own];
-      const T* UXp = &lds[(S_UX + s1) * PLANE + own];
-      const T* UY0 = &lds[(S_UY + s0) * PLANE + own];
-      const T* UYm = &lds[(S_UY + sm) * PLANE + own];
-      const T* UYp = &lds[(S_UY + s1) * PLANE + own];
-      const T* UZ0 = &lds[(S_UZ + s0) * PLANE + own];
-      const T* UZm = &lds[(S_UZ + sm) * PLANE + own];
-      const T* UZp = &lds[(S_UZ + s1) * PLANE + own];
-      const T* PH0 = &lds[(S_PH + s0) * PLANE + own];
-      const T* PHm = &lds[(S_PH + sm) * PLANE + own];
-      const T* ET0 = &lds[(S_ET + s0) * PLANE + own];
-      const T* ETm = &lds[(S_ET + sm) * PLANE + own];
-      const T* ETp = &lds[(S_ET + s1) * PLANE + own];
-      const T* NU0 = &lds[(S_NU + s0) * PLANE + own];
-      const T* NUm = &lds[(S_NU + sm) * PLANE + own];
-      const T* NUp = &lds[(S_NU + s1) * PLANE + own];
-      const T* MU = &lds[S_MU * PLANE + own];
-      const T* DV = &lds[S_DV * PLANE + own];
+      const T* P0 = L0 + (S_P + S0) * PLANE;
+      const T* Pm = L0 + (S_P + SM) * PLANE;
+      const T* Pp = L0 + (S_P + SP) * PLANE;
+      const T* UX0 = L0 + (S_UX + S0) * PLANE;
+      const T* UXm = L0 + (S_UX + SM) * PLANE;
+      const T* UXp = L0 + (S_UX + SP) * PLANE;
+      const T* UY0 = L0 + (S_UY + S0) * PLANE;
+      const T* UYm = L0 + (S_UY + SM) * PLANE;
+      const T* UYp = L0 + (S_UY + SP) * PLANE;
+      const T* UZ0 = L0 + (S_UZ + S0) * PLANE;
+      const T* UZm = L0 + (S_UZ + SM) * PLANE;
+      const T* UZp = L0 + (S_UZ + SP) * PLANE;
+      const T* PH0 = L0 + (S_PH + S0) * PLANE;
+      const T* PHm = L0 + (S_PH + SM) * PLANE;
+      const T* ET0 = L0 + (S_ET + S0) * PLANE;
+      const T* ETm = L0 + (S_ET + SM) * PLANE;
+      const T* ETp = L0 + (S_ET + SP) * PLANE;
+      const T* NU0 = L0 + (S_NU + S0) * PLANE;
+      const T* NUm = L0 + (S_NU + SM) * PLANE;
+      const T* NUp = L0 + (S_NU + SP) * PLANE;
+      const T* MU = L0 + S_MU * PLANE;
+      const T* DV = L0 + S_DV * PLANE;
 
       // axisymmetric radii of row k (Z radial): centre r_k, faces R_k = k, R_{k+1}
       const T rk = T(k) + T(0.5);
       const T Rk = T(k), Rk1 = T(k) + T(1);
       const T inv_rk = T(1) / rk;
 
-      // ---- pressure equation at the cell centre ----
+      // ---- pressure equation at the cell centre:
+      // dp/dt = -rho cs^2 D + sum [nu_{+1/2} (p_+ - p) - nu_{-1/2} (p - p_-)]
       const T pc = P0[0], nuc = NU0[0];
-      T diff = T(0.5) * (nuc + NU0[1]) * (P0[1] - pc) - T(0.5) * (nuc + NU0[-1]) * (pc - P0[-1]);
-      if (DIM == 3)
-        diff += T(0.5) * (nuc + NU0[EY]) * (P0[EY] - pc) - T(0.5) * (nuc + NU0[-EY]) * (pc - P0[-EY]);
+      T diff = (nuc + NU0[1]) * (P0[1] - pc) - (nuc + NU0[-1]) * (pc - P0[-1]);
+      if (DIM == 3) diff += (nuc + NU0[EY]) * (P0[EY] - pc) - (nuc + NU0[-EY]) * (pc - P0[-EY]);
       {
-        const T fp = T(0.5) * (nuc + NUp[0]) * (Pp[0] - pc);
-        const T fm = T(0.5) * (nuc + NUm[0]) * (pc - Pm[0]);
+        const T fp = (nuc + NUp[0]) * (Pp[0] - pc);
+        const T fm = (nuc + NUm[0]) * (pc - Pm[0]);
         diff += AXI ? (Rk1 * fp - Rk * fm) * inv_rk : fp - fm;
       }
-      const T Lp = -rho_of(c, PH0[0]) * c.cs2 * DV[0] + diff;
+      const T fc = clamp1(PH0[0]);
+      const T Lp = -fma(T(2) * c.rho_hb, fc, c.rho_a) * c.cs2 * DV[0] + T(0.5) * diff;
 
-      // ---- momentum at an in-plane face (normal A; offset ea, other in-plane
-      //      axis B with offset eb in 3-D, Z transverse) ----
-      auto face_inplane = [&](const T* UA0, const T* UAm, const T* UAp, const T* UB0, int ea,
-                              int eb, T gA) -> T {
+      // ---- momentum at an in-plane face (normal A with LDS offset ea, other
+      // in-plane axis B with offset eb in 3-D, Z transverse) ----
+      auto face_inplane = [&](const T* UA0, const T* UAm, const T* UAp, const T* UB0, int ea, int eb,
+                              T gA, T gm, T g0, T gp) -> T {
         const T ua = UA0[0];
         const T phc = PH0[0], phl = PH0[-ea];
-        const T rho_f = T(0.5) * (rho_of(c, phl) + rho_of(c, phc));
+        const T rho_f = fma(c.rho_hb, fc + clamp1(phl), c.rho_a);  // mean of the two cells
         const T eh = ET0[0], el = ET0[-ea];
-        // convection
-        T C = ua * (UA0[ea] - UA0[-ea]) * T(0.5);
+        // twice the convection: u d_a u + ubar_b d_b u + ubar_z d_z u
+        T conv = ua * (UA0[ea] - UA0[-ea]);
         {
-          const T uzb = T(0.25) * ((UZ0[0] + UZ0[-ea]) + (UZp[0] + UZp[-ea]));
-          C += uzb * (UAp[0] - UAm[0]) * T(0.5);
+          const T sz = (UZ0[0] + UZ0[-ea]) + (UZp[0] + UZp[-ea]);
+          T tr = sz * (UAp[0] - UAm[0]);
+          if (DIM == 3) {
+            const T sb = (UB0[0] + UB0[-ea]) + (UB0[eb] + UB0[eb - ea]);
+            tr += sb * (UA0[eb] - UA0[-eb]);
+          }
+          conv += T(0.25) * tr;
         }
-        if (DIM == 3) {
-          const T ubb = T(0.25) * ((UB0[0] + UB0[-ea]) + (UB0[eb] + UB0[eb - ea]));
-          C += ubb * (UA0[eb] - UA0[-eb]) * T(0.5);
-        }
-        // viscous stress divergence, bulk viscosity eta_b = eta
+        // viscous stress divergence with corner-averaged eta, bulk eta_b = eta
         T V = T(2) * (eh * (UA0[ea] - ua) - el * (ua - UA0[-ea]));
+        T Vt;
         {
-          const T ep = T(0.25) * ((eh + ETp[0]) + (el + ETp[-ea]));
-          const T em = T(0.25) * ((eh + ETm[0]) + (el + ETm[-ea]));
+          const T ep = (eh + ETp[0]) + (el + ETp[-ea]);
+          const T em = (eh + ETm[0]) + (el + ETm[-ea]);
           const T fp = ep * ((UAp[0] - ua) + (UZp[0] - UZp[-ea]));
           const T fm = em * ((ua - UAm[0]) + (UZ0[0] - UZ0[-ea]));
-          V += AXI ? (Rk1 * fp - Rk * fm) * inv_rk : fp - fm;
+          Vt = AXI ? (Rk1 * fp - Rk * fm) * inv_rk : fp - fm;
         }
         if (DIM == 3) {
-          const T ep = T(0.25) * ((eh + ET0[eb]) + (el + ET0[eb - ea]));
-          const T em = T(0.25) * ((eh + ET0[-eb]) + (el + ET0[-eb - ea]));
+          const T ep = (eh + ET0[eb]) + (el + ET0[eb - ea]);
+          const T em = (eh + ET0[-eb]) + (el + ET0[-eb - ea]);
           const T fp = ep * ((UA0[eb] - ua) + (UB0[eb] - UB0[eb - ea]));
           const T fm = em * ((ua - UA0[-eb]) + (UB0[0] - UB0[-ea]));
-          V += fp - fm;
+          Vt += fp - fm;
         }
-        V += eh * DV[0] - el * DV[-ea];
-        // transversely averaged pressure gradient, difference-first
-        T G;
-        if (DIM == 2) {
-          const T d0 = P0[0] - P0[-ea], dp = Pp[0] - Pp[-ea], dm = Pm[0] - Pm[-ea];
-          G = (T(4) * d0 + (dp + dm)) * T(1.0 / 6.0);
-        } else {
-          const T r0 = T(4) * (P0[0] - P0[-ea]) + ((P0[eb] - P0[eb - ea]) + (P0[-eb] - P0[-eb - ea]));
-          const T rp = T(4) * (Pp[0] - Pp[-ea]) + ((Pp[eb] - Pp[eb - ea]) + (Pp[-eb] - Pp[-eb - ea]));
-          const T rm = T(4) * (Pm[0] - Pm[-ea]) + ((Pm[eb] - Pm[eb - ea]) + (Pm[-eb] - Pm[-eb - ea]));
-          G = (T(4) * r0 + (rp + rm)) * T(1.0 / 36.0);
-        }
-        const T S = -c.sigma * (phc + phl) * (MU[0] - MU[-ea]) * T(0.5);
+        V += T(0.25) * Vt + (eh * DV[0] - el * DV[-ea]);
+        // transversely averaged pressure gradient from the carried partial sums
+        const T G = (T(4) * g0 + (gp + gm)) * (DIM == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0));
+        const T S = c.hsig * (phc + phl) * (MU[0] - MU[-ea]);
         const T B = (rho_f - c.rho_ref) * gA;
-        return -C + (-G + V + S + B) * recip(rho_f);
+        return fma(T(-0.5), conv, (-G + V + S + B) * recip(rho_f));
       };
 
-      const T LuX = face_inplane(UX0, UXm, UXp, UY0, 1, EY, c.g[0]);
+      const T LuX = face_inplane(UX0, UXm, UXp, UY0, 1, EY, c.g[0], gx_m, gx_0, gx_p);
       T LuY = T(0);
-      if (DIM == 3) LuY = face_inplane(UY0, UYm, UYp, UX0, EY, 1, c.g[1]);
+      if (DIM == 3) LuY = face_inplane(UY0, UYm, UYp, UX0, EY, 1, c.g[1], gy_m, gy_0, gy_p);
 
       // ---- momentum at the Z face between planes k-1 and k ----
       T LuZ = T(0);
@@ -262,16 +320,17 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
       if (!bZ) {
         const T uz = UZ0[0];
         const T phc = PH0[0], phl = PHm[0];
-        const T rho_f = T(0.5) * (rho_of(c, phl) + rho_of(c, phc));
+        const T rho_f = fma(c.rho_hb, fc + clamp1(phl), c.rho_a);
         const T eh = ET0[0], el = ETm[0];
-        T C = uz * (UZp[0] - UZm[0]) * T(0.5);
+        T conv = uz * (UZp[0] - UZm[0]);
         {
-          const T uxb = T(0.25) * ((UX0[0] + UXm[0]) + (UX0[1] + UXm[1]));
-          C += uxb * (UZ0[1] - UZ0[-1]) * T(0.5);
-        }
-        if (DIM == 3) {
-          const T uyb = T(0.25) * ((UY0[0] + UYm[0]) + (UY0[EY] + UYm[EY]));
-          C += uyb * (UZ0[EY] - UZ0[-EY]) * T(0.5);
+          const T sx = (UX0[0] + UXm[0]) + (UX0[1] + UXm[1]);
+          T tr = sx * (UZ0[1] - UZ0[-1]);
+          if (DIM == 3) {
+            const T sy = (UY0[0] + UYm[0]) + (UY0[EY] + UYm[EY]);
+            tr += sy * (UZ0[EY] - UZ0[-EY]);
+          }
+          conv += T(0.25) * tr;
         }
         T V;
         if (AXI) {
@@ -282,21 +341,22 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
         } else {
           V = T(2) * (eh * (UZp[0] - uz) - el * (uz - UZm[0]));
         }
+        T Vt;
         {
-          const T ep = T(0.25) * ((eh + ET0[1]) + (el + ETm[1]));
-          const T em = T(0.25) * ((eh + ET0[-1]) + (el + ETm[-1]));
+          const T ep = (eh + ET0[1]) + (el + ETm[1]);
+          const T em = (eh + ET0[-1]) + (el + ETm[-1]);
           const T fp = ep * ((UZ0[1] - uz) + (UX0[1] - UXm[1]));
           const T fm = em * ((uz - UZ0[-1]) + (UX0[0] - UXm[0]));
-          V += fp - fm;
+          Vt = fp - fm;
         }
         if (DIM == 3) {
-          const T ep = T(0.25) * ((eh + ET0[EY]) + (el + ETm[EY]));
-          const T em = T(0.25) * ((eh + ET0[-EY]) + (el + ETm[-EY]));
+          const T ep = (eh + ET0[EY]) + (el + ETm[EY]);
+          const T em = (eh + ET0[-EY]) + (el + ETm[-EY]);
           const T fp = ep * ((UZ0[EY] - uz) + (UY0[EY] - UYm[EY]));
           const T fm = em * ((uz - UZ0[-EY]) + (UY0[0] - UYm[0]));
-          V += fp - fm;
+          Vt += fp - fm;
         }
-        V += eh * DV[0] - el * dv_prev;
+        V += T(0.25) * Vt + (eh * DV[0] - el * dv_prev);
         T G;
         if (DIM == 2) {
           G = (T(4) * (P0[0] - Pm[0]) + ((P0[1] - Pm[1]) + (P0[-1] - Pm[-1]))) * T(1.0 / 6.0);
@@ -306,28 +366,27 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
           };
           G = (T(4) * row(0) + (row(EY) + row(-EY))) * T(1.0 / 36.0);
         }
-        const T S = -c.sigma * (phc + phl) * (MU[0] - mu_prev) * T(0.5);
+        const T S = c.hsig * (phc + phl) * (MU[0] - mu_prev);
         const T B = (rho_f - c.rho_ref) * c.g[2];
-        LuZ = -C + (-G + V + S + B) * recip(rho_f);
+        LuZ = fma(T(-0.5), conv, (-G + V + S + B) * recip(rho_f));
       }
 
-      // ---- Shu-Osher combination of the stage ----
+      // ---- Shu-Osher combination of the stage (increment form) ----
       const bool bX = (i == 0 && g.bc[0] != BC_PERIODIC);
       const bool bY = (DIM == 3) && (j == 0 && g.bc[2] != BC_PERIODIC);
       const size_t ci = ((size_t)k * ny + j) * nx + i;
-      const T dt = c.dt;
       T q[4] = {P0[0], UX0[0], (DIM == 3) ? UY0[0] : T(0), UZ0[0]};
       T L[4] = {Lp, LuX, LuY, LuZ};
       T out[4];
       T old[4] = {T(0), T(0), T(0), T(0)};
+      if (!QN_EARLY) fetch_qn(k, qn_cur);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if (DIM == 2 && f == 2) continue;
         if (STAGE == 1) {
-          out[f] = q[f] + dt * L[f];
+          out[f] = fma(dt, L[f], q[f]);
         } else {
-          old[f] = A.qn[f][ci];
-          // Shu-Osher combination in increment form: exact for L = 0
+          old[f] = qn_cur[f];
           if (STAGE == 2)
             out[f] = old[f] + T(0.25) * ((q[f] - old[f]) + dt * L[f]);
           else
@@ -347,18 +406,31 @@ __global__ __launch_bounds__(TX* TY) void flow_stage_kernel(FlowArgs<T> A) {
         A.usum[2][ci] = old[3] + out[3];
       }
     }
-    mu_prev = lds[S_MU * PLANE + own];
-    dv_prev = lds[S_DV * PLANE + own];
-    __syncthreads();
+    mu_prev = L0[S_MU * PLANE];
+    dv_prev = L0[S_DV * PLANE];
+
+    gx_m = gx_0;
+    gx_0 = gx_p;
+    gy_m = gy_0;
+    gy_0 = gy_p;
+  };
+
+  for (int k = z0; k < z1; k += 3) {
+    step(std::integral_constant<int, 0>{}, k);
+    if (k + 1 < z1) step(std::integral_constant<int, 1>{}, k + 1);
+    if (k + 2 < z1) step(std::integral_constant<int, 2>{}, k + 2);
   }
 }
 
 template <typename T, int DIM, bool AXI, int STAGE>
 static hipError_t launch_flow_t(const FlowArgs<T>& a, hipStream_t s) {
   constexpr int TX = FlowTile<DIM>::TX, TY = FlowTile<DIM>::TY;
-  dim3 grid((a.g.n[0] + TX - 1) / TX, (a.g.n[1] + TY - 1) / TY,
-            (a.g.n[2] + a.g.zchunk - 1) / a.g.zchunk);
-  hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY>), grid, dim3(TX * TY), 0, s, a);
+  FlowArgs<T> b = a;
+  b.g.nb[0] = (a.g.n[0] + TX - 1) / TX;
+  b.g.nb[1] = (a.g.n[1] + TY - 1) / TY;
+  b.g.nb[2] = (a.g.n[2] + a.g.zchunk - 1) / a.g.zchunk;
+  const unsigned nblk = (unsigned)(b.g.nb[0] * b.g.nb[1] * b.g.nb[2]);
+  hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, b);
   return hipGetLastError();
 }
 

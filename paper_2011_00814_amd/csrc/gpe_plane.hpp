@@ -6,50 +6,77 @@
 
 namespace gpe {
 
-// Per-thread precomputed in-plane addressing of the halo'd plane region
-// [-H, TX+H2) x [-H, TY+H2) of a tile (H = 2 low-side halo cells).  For each
-// load pass the thread keeps the in-plane offset of a cell-centred value, of
-// an X-face and of a Y-face value, and the in-plane signs of the X-, Y- and
-// Z-directed velocity components.
+// In-plane addressing of the halo'd plane region [-2, PX-2) x [-2, PY-2) of a
+// tile (relative to its first column x0 and row y0).  A tile whose region
+// lies inside the domain ("interior") addresses every field at the plain
+// cell offset with unit signs.  Other tiles map each position through the
+// ghost rules: a cell-centred value, an X-face and a Y-face value get their
+// own offsets, and the X-, Y- and Z-directed velocity components their
+// in-plane signs.  Only the cell offset is kept per load pass; the face
+// offsets and signs of boundary tiles are recomputed when a plane is loaded,
+// which keeps the register footprint of the common interior case small.
 template <typename T, int DIM, int PX, int PY, int NT>
 struct PlaneMap {
   static constexpr int PLANE = PX * PY;
   static constexpr int NPASS = (PLANE + NT - 1) / NT;
-  int off_c[NPASS], off_x[NPASS], off_y[NPASS];
-  T sg_x[NPASS], sg_y[NPASS], sg_z[NPASS];
+  int off_c[NPASS];
   bool ok[NPASS];
+  bool interior;
+  int x0, y0;
 
-  __device__ __forceinline__ void init(const Grid& g, int x0, int y0) {
+  struct Pos {
+    int oc, ox, oy;  // in-plane offsets: cell value, X-face value, Y-face value
+    T sx, sy, sz;    // in-plane signs of the X-, Y-, Z-directed components
+  };
+
+  __device__ __forceinline__ void init(const Grid& g, int x0_, int y0_) {
+    x0 = x0_;
+    y0 = y0_;
     const int nx = g.n[0], ny = g.n[1];
+    interior = x0 - 2 >= 0 && x0 - 2 + PX - 1 <= nx - 1;
+    if (DIM == 3) interior = interior && y0 - 2 >= 0 && y0 - 2 + PY - 1 <= ny - 1;
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
-      const int lp = (int)threadIdx.x + p * NT;
-      const int lx = lp % PX, ly = lp / PX;
-      const int gx = x0 - 2 + lx;
-      const int gy = (DIM == 3) ? y0 - 2 + ly : 0;
-      bool ok_ = lp < PLANE && gx >= -2 && gx <= nx + 1;
-      if (DIM == 3) ok_ = ok_ && gy >= -2 && gy <= ny + 1;
-      ok[p] = ok_;
-      off_c[p] = off_x[p] = off_y[p] = 0;
-      sg_x[p] = sg_y[p] = sg_z[p] = T(0);
-      if (!ok_) continue;
-      int rx, ry = 0, fxs, fys = 1;
-      const int mx = map_cell(gx, nx, g.bc[0], g.bc[1], rx);
-      const int fx = map_face(gx, nx, g.bc[0], fxs);
-      int my = 0, fy = 0;
-      if (DIM == 3) {
-        my = map_cell(gy, ny, g.bc[2], g.bc[3], ry);
-        fy = map_face(gy, ny, g.bc[2], fys);
-      }
-      const int wx = (rx == BC_WALL) ? -1 : 1;
-      const int wy = (ry == BC_WALL) ? -1 : 1;
-      off_c[p] = my * nx + mx;
-      off_x[p] = my * nx + fx;
-      off_y[p] = fy * nx + mx;
-      sg_x[p] = T(fxs * wy);
-      sg_y[p] = T(fys * wx);
-      sg_z[p] = T(wx * wy);
+      const Pos q = map(g, p, ok[p]);
+      off_c[p] = q.oc;
     }
+  }
+
+  // full ghost-rule mapping of load pass p of this thread
+  __device__ __forceinline__ Pos map(const Grid& g, int p, bool& ok_) const {
+    const int nx = g.n[0], ny = g.n[1];
+    const int lp = (int)threadIdx.x + p * NT;
+    const int lx = lp % PX, ly = lp / PX;
+    const int gx = x0 - 2 + lx;
+    const int gy = (DIM == 3) ? y0 - 2 + ly : 0;
+    Pos q{0, 0, 0, T(0), T(0), T(0)};
+    ok_ = lp < PLANE && gx >= -2 && gx <= nx + 1;
+    if (DIM == 3) ok_ = ok_ && gy >= -2 && gy <= ny + 1;
+    if (!ok_) return q;
+    int rx, ry = 0, fxs, fys = 1;
+    const int mx = map_cell(gx, nx, g.bc[0], g.bc[1], rx);
+    const int fx = map_face(gx, nx, g.bc[0], fxs);
+    int my = 0, fy = 0;
+    if (DIM == 3) {
+      my = map_cell(gy, ny, g.bc[2], g.bc[3], ry);
+      fy = map_face(gy, ny, g.bc[2], fys);
+    }
+    const int wx = (rx == BC_WALL) ? -1 : 1;
+    const int wy = (ry == BC_WALL) ? -1 : 1;
+    q.oc = my * nx + mx;
+    q.ox = my * nx + fx;
+    q.oy = fy * nx + mx;
+    q.sx = T(fxs * wy);
+    q.sy = T(fys * wx);
+    q.sz = T(wx * wy);
+    return q;
+  }
+
+  // addressing of load pass p (valid when ok[p])
+  __device__ __forceinline__ Pos pos(const Grid& g, int p) const {
+    if (interior) return Pos{off_c[p], off_c[p], off_c[p], T(1), T(1), T(1)};
+    bool dummy;
+    return map(g, p, dummy);
   }
 };
 
