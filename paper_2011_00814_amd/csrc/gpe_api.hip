@@ -57,6 +57,7 @@ struct gpe_state {
   int sticky;
   hipGraphExec_t graph;
   bool graph_ok;
+  int ncu;                 // compute units of the device the handle runs on
 };
 
 namespace {
@@ -223,7 +224,11 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
   };
   FlowArgs<T> f;
   f.g = s->grid;
-  f.g.zchunk = (s->dim == 3) ? gpe::FlowTile<3>::ZC : gpe::FlowTile<2>::ZC;
+  f.g.zchunk = (s->dim == 3)
+                   ? gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, T>::TX, gpe::FlowTile<3, T>::TY,
+                                        gpe::FlowTile<3, T>::BPC, s->ncu)
+                   : gpe::choose_zchunk(s->grid.n, gpe::FlowTile<2, T>::TX, gpe::FlowTile<2, T>::TY,
+                                        gpe::FlowTile<2, T>::BPC, s->ncu);
   f.c = c;
   f.phi = buf<T>(s, B_PHI);
   for (int a = 0; a < 3; ++a) f.usum[a] = buf<T>(s, B_US + a);
@@ -242,7 +247,11 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
   }
   ChArgs<T> h;
   h.g = s->grid;
-  h.g.zchunk = (s->dim == 3) ? gpe::ChTile<3>::ZC : gpe::ChTile<2>::ZC;
+  h.g.zchunk = (s->dim == 3)
+                   ? gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, T>::TX, gpe::ChTile<3, T>::TY,
+                                        gpe::ChTile<3, T>::BPC, s->ncu)
+                   : gpe::choose_zchunk(s->grid.n, gpe::ChTile<2, T>::TX, gpe::ChTile<2, T>::TY,
+                                        gpe::ChTile<2, T>::BPC, s->ncu);
   h.c = c;
   for (int a = 0; a < 3; ++a) h.usum[a] = buf<T>(s, B_US + a);
   T* phi = buf<T>(s, B_PHI);
@@ -452,6 +461,14 @@ int gpe_init_state(const gpe_params* p, void* d_workspace, size_t bytes, void* h
     s->grid.bc[5] = p->bc[3];
   }
   s->grid.zchunk = 1;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      ncu = 256;
+    s->ncu = ncu;
+  }
   bool need[B_COUNT];
   needed(p, need);
   size_t o = 0;

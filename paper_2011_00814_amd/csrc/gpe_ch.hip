@@ -66,6 +66,7 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
       if (pm.ok[p]) {
         const auto q = pm.pos(g, p);
         if (kf >= -2) r_f[p] = bf[q.oc];
+        if (!pm.inner_row(p)) continue;  // face sums are never read on the outermost row
         if (kxy >= -2) {
           r_x[p] = bx[q.ox] * (q.sx * zxy.tan);
           if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * zxy.tan);
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
 
 template <typename T, int DIM, bool AXI, int STAGE>
 static hipError_t launch_ch_t(const ChArgs<T>& a, hipStream_t s) {
-  constexpr int TX = ChTile<DIM>::TX, TY = ChTile<DIM>::TY;
+  constexpr int TX = ChTile<DIM, T>::TX, TY = ChTile<DIM, T>::TY;
   ChArgs<T> b = a;
   b.g.nb[0] = (a.g.n[0] + TX - 1) / TX;
   b.g.nb[1] = (a.g.n[1] + TY - 1) / TY;

@@ -152,19 +152,38 @@ hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, hipStream_
 template <typename T>
 hipError_t launch_ch(const ChArgs<T>& a, int geometry, int stage, hipStream_t s);
 
-// Work-group tile shapes (X x Y columns, marched along Z).
-template <int DIM>
+// Work-group tile shapes (X x Y columns, marched along Z) and the number of
+// work-groups per CU their LDS footprint allows.  FP32 3-D tiles are 32 x 16
+// (512 threads, halo area 1.29x the tile); FP64 3-D tiles are 32 x 8.
+template <int DIM, typename T>
 struct FlowTile;
+template <typename T>
+struct FlowTile<2, T> { static constexpr int TX = 64, TY = 1, BPC = 8; };
 template <>
-struct FlowTile<2> { static constexpr int TX = 64, TY = 1, ZC = 16; };
+struct FlowTile<3, float> { static constexpr int TX = 32, TY = 16, BPC = 2; };
 template <>
-struct FlowTile<3> { static constexpr int TX = 32, TY = 8, ZC = 32; };
+struct FlowTile<3, double> { static constexpr int TX = 32, TY = 8, BPC = 2; };
 
-template <int DIM>
+template <int DIM, typename T>
 struct ChTile;
+template <typename T>
+struct ChTile<2, T> { static constexpr int TX = 64, TY = 1, BPC = 8; };
 template <>
-struct ChTile<2> { static constexpr int TX = 64, TY = 1, ZC = 16; };
+struct ChTile<3, float> { static constexpr int TX = 32, TY = 16, BPC = 2; };
 template <>
-struct ChTile<3> { static constexpr int TX = 32, TY = 8, ZC = 32; };
+struct ChTile<3, double> { static constexpr int TX = 32, TY = 8, BPC = 2; };
+
+// Planes per work-group along Z: enough Z chunks that the whole grid is
+// resident in one round of work-groups (all tiles then march through the
+// same planes together and share halo rows in L2), but at least 8 planes.
+inline int choose_zchunk(const int n[3], int tx, int ty, int bpc, int ncu) {
+  const long tiles = (long)((n[0] + tx - 1) / tx) * ((n[1] + ty - 1) / ty);
+  long chunks = (long)ncu * bpc / tiles;
+  if (chunks < 1) chunks = 1;
+  int zc = (int)((n[2] + chunks - 1) / chunks);
+  if (zc < 8) zc = 8;
+  if (zc > n[2]) zc = n[2];
+  return zc;
+}
 
 }  // namespace gpe

@@ -75,11 +75,13 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       r_p[p] = r_x[p] = r_y[p] = r_z[p] = r_f[p] = T(0);
       if (pm.ok[p]) {
         const auto q = pm.pos(g, p);
-        r_p[p] = bp[q.oc];
-        r_x[p] = bx[q.ox] * (q.sx * z.tan);
-        if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * z.tan);
-        r_z[p] = bz[q.oc] * (q.sz * z.nrm);
         r_f[p] = bf[q.oc];
+        if (pm.inner_row(p)) {  // p and u are never read on the outermost row
+          r_p[p] = bp[q.oc];
+          r_x[p] = bx[q.ox] * (q.sx * z.tan);
+          if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * z.tan);
+          r_z[p] = bz[q.oc] * (q.sz * z.nrm);
+        }
       }
     }
   };
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
 
 template <typename T, int DIM, bool AXI, int STAGE>
 static hipError_t launch_flow_t(const FlowArgs<T>& a, hipStream_t s) {
-  constexpr int TX = FlowTile<DIM>::TX, TY = FlowTile<DIM>::TY;
+  constexpr int TX = FlowTile<DIM, T>::TX, TY = FlowTile<DIM, T>::TY;
   FlowArgs<T> b = a;
   b.g.nb[0] = (a.g.n[0] + TX - 1) / TX;
   b.g.nb[1] = (a.g.n[1] + TY - 1) / TY;

@@ -72,6 +72,14 @@ struct PlaneMap {
     return q;
   }
 
+  // false for positions of the outermost low halo row (ly = 0) in 3-D,
+  // which only the phase field needs
+  __device__ __forceinline__ bool inner_row(int p) const {
+    if (DIM == 2) return true;
+    const int lp = (int)threadIdx.x + p * NT;
+    return lp >= PX;
+  }
+
   // addressing of load pass p (valid when ok[p])
   __device__ __forceinline__ Pos pos(const Grid& g, int p) const {
     if (interior) return Pos{off_c[p], off_c[p], off_c[p], T(1), T(1), T(1)};

@@ -75,6 +75,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2011_00814_amd.build`")
+        # torch provides the device memory and streams: load its HIP runtime
+        # first so that the library binds to the same runtime instance
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.gpe_params_from_dimensionless.argtypes = [ctypes.POINTER(gpe_problem), ctypes.POINTER(gpe_params)]
