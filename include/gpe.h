@@ -184,7 +184,10 @@ int gpe_set_step_time(gpe_state* s, int64_t step, double t);
 
 /* Average device duration of every kernel of the step, measured with HIP
  * events around each launch over nsteps eager steps on the handle's stream
- * (the state advances by nsteps).  names[i] receives a static string,
+ * (the state advances by nsteps).  The steps are enqueued back to back with
+ * one event before each step and one after every kernel, and the call
+ * blocks until they have run; the per-kernel means therefore add up to the
+ * device time per step.  names[i] receives a static string,
  * ms[i] the mean duration in milliseconds, bytes[i] the algorithmic HBM
  * bytes of one launch (each field read once and written once).  Returns
  * the number of kernels (<= max) or a negative gpe_error. */

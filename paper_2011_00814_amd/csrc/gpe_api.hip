@@ -208,9 +208,10 @@ Consts<T> make_consts(const gpe_params* p, int dim) {
 }
 
 // ---- kernel sequence of one time step ----------------------------------
+// Chained timing events: one before the first kernel of a step and one after
+// every kernel, so kernel q of a step lasts from event q to event q + 1.
 struct KernelTimer {
-  bool on = false;
-  hipEvent_t ev[2 * 16];
+  hipEvent_t* ev = nullptr;  // this step's events
   int n = 0;
 };
 
@@ -220,8 +221,9 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
   const Consts<T> c = make_consts<T>(&s->P, s->dim);
   hipError_t e = hipSuccess;
   auto mark = [&]() {
-    if (kt && kt->on) (void)hipEventRecord(kt->ev[kt->n++], s->stream);
+    if (kt) (void)hipEventRecord(kt->ev[kt->n++], s->stream);
   };
+  mark();
   FlowArgs<T> f;
   f.g = s->grid;
   f.g.zchunk = (s->dim == 3)
@@ -240,7 +242,6 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
       f.qn[q] = buf<T>(s, B_Q0 + q);
       f.dst[q] = buf<T>(s, dst + q);
     }
-    mark();
     e = gpe::launch_flow<T>(f, geom, st, s->stream);
     mark();
     if (e != hipSuccess) return e;
@@ -271,7 +272,6 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
     h.out = st.out;
     h.phis = phi;
     h.acc = acc;
-    mark();
     e = gpe::launch_ch<T>(h, geom, st.stage, s->stream);
     mark();
     if (e != hipSuccess) return e;
@@ -580,29 +580,33 @@ int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, 
   static const char* n2[5] = {"flow_stage1", "flow_stage2", "flow_stage3", "ch_rk2_stage1",
                               "ch_rk2_stage2"};
   // algorithmic HBM traffic per launch, in fields of one cell
-  const int d = s->dim;
   const double f3[7] = {9, 13, 16, 6, 8, 8, 6};
   const double f2[5] = {7, 10, 12, 4, 5};
-  (void)d;
-  KernelTimer kt;
-  kt.on = true;
-  for (int q = 0; q < 2 * nk; ++q)
-    if (hipEventCreate(&kt.ev[q]) != hipSuccess) return GPE_EHIP;
-  std::vector<double> acc(nk, 0.0);
+  // all steps are enqueued back to back (no host synchronisation between
+  // them), then read once
+  std::vector<hipEvent_t> ev((size_t)nsteps * (nk + 1), nullptr);
   int rc = GPE_OK;
+  for (auto& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) { rc = GPE_EHIP; break; }
+  std::vector<double> acc(nk, 0.0);
   for (int64_t st = 0; st < nsteps && rc == GPE_OK; ++st) {
-    kt.n = 0;
+    KernelTimer kt;
+    kt.ev = ev.data() + (size_t)st * (nk + 1);
     if (enqueue_step(s, &kt) != hipSuccess) { rc = GPE_EHIP; break; }
-    if (hipStreamSynchronize(s->stream) != hipSuccess) { rc = GPE_EHIP; break; }
-    for (int q = 0; q < nk; ++q) {
-      float t = 0;
-      (void)hipEventElapsedTime(&t, kt.ev[2 * q], kt.ev[2 * q + 1]);
-      acc[q] += t;
-    }
     s->step += 1;
   }
+  if (rc == GPE_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = GPE_EHIP;
+  for (int64_t st = 0; st < nsteps && rc == GPE_OK; ++st) {
+    const hipEvent_t* e = ev.data() + (size_t)st * (nk + 1);
+    for (int q = 0; q < nk; ++q) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, e[q], e[q + 1]) != hipSuccess) { rc = GPE_EHIP; break; }
+      acc[q] += t;
+    }
+  }
   s->t = s->step * s->P.dt;
-  for (int q = 0; q < 2 * nk; ++q) (void)hipEventDestroy(kt.ev[q]);
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
   if (rc) return rc;
   for (int q = 0; q < nk; ++q) {
     names[q] = s->dim == 3 ? n3[q] : n2[q];

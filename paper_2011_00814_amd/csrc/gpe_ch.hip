@@ -18,8 +18,13 @@
 
 namespace gpe {
 
+// Occupancy target: 4 waves per SIMD in FP32 (<= 128 VGPRs, which the LDS
+// footprint of two work-groups per CU matches); FP64 is LDS-limited to 2.
+template <typename T>
+struct ChOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 2; };
+
 template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
+__global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T> A) {
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 4;                  // in-plane X range [-2, TX+1]
   constexpr int PY = (DIM == 3) ? TY + 4 : 1;
@@ -50,8 +55,10 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
 
   // Staging of the planes an iteration needs (phi of plane k+2, the X/Y face
   // sums of plane k+1, the Z face sums of plane k+2) is software-pipelined:
-  // fetch() issues the global loads into registers (ghost rules applied),
-  // commit() writes them to LDS one iteration later.  A plane index below -2
+  // fetch() issues the global loads into registers one iteration ahead,
+  // commit() applies the ghost-rule signs and writes them to LDS.  No
+  // arithmetic touches a loaded value before commit(), so the loads stay in
+  // flight while the current plane is processed.  A plane index below -2
   // marks "nothing to stage".
   T r_f[pm.NPASS], r_x[pm.NPASS], r_y[pm.NPASS], r_z[pm.NPASS];
   auto fetch = [&](int kf, int kxy, int kz) {
@@ -68,24 +75,26 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
         if (kf >= -2) r_f[p] = bf[q.oc];
         if (!pm.inner_row(p)) continue;  // face sums are never read on the outermost row
         if (kxy >= -2) {
-          r_x[p] = bx[q.ox] * (q.sx * zxy.tan);
-          if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * zxy.tan);
+          r_x[p] = bx[q.ox];
+          if (DIM == 3) r_y[p] = by[q.oy];
         }
-        if (kz >= -2) r_z[p] = bz[q.oc] * (q.sz * zz.nrm);
+        if (kz >= -2) r_z[p] = bz[q.oc];
       }
     }
   };
-  auto commit = [&](int sf, int sz, bool do_f, bool do_xy, bool do_z) {
+  auto commit = [&](int kxy, int kz, int sf, int sz, bool do_f, bool do_xy, bool do_z) {
+    const ZMap<T> zxy(g, kxy), zz(g, kz);
 #pragma unroll
     for (int p = 0; p < pm.NPASS; ++p) {
       const int lp = (int)threadIdx.x + p * NT;
       if (lp >= PLANE) continue;
+      const auto q = pm.pos(g, p);  // signs (all +1 inside an interior tile)
       if (do_f) lds[(S_PH + sf) * PLANE + lp] = r_f[p];
       if (do_xy) {
-        lds[S_SX * PLANE + lp] = r_x[p];
-        if (DIM == 3) lds[S_SY * PLANE + lp] = r_y[p];
+        lds[S_SX * PLANE + lp] = r_x[p] * (q.sx * zxy.tan);
+        if (DIM == 3) lds[S_SY * PLANE + lp] = r_y[p] * (q.sy * zxy.tan);
       }
-      if (do_z) lds[(S_SZ + sz) * PLANE + lp] = r_z[p];
+      if (do_z) lds[(S_SZ + sz) * PLANE + lp] = r_z[p] * (q.sz * zz.nrm);
     }
   };
 
@@ -163,8 +172,9 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
     }
   };
 
-  // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP)
-  auto output = [&](int k, auto s0) {
+  // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP);
+  // phc = phi(k) at the own cell
+  auto output = [&](int k, auto s0, T phc, T ps, T ac) {
     constexpr int S0 = decltype(s0)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     const T* M0 = L0 + (S_MU + S0) * PLANE;
@@ -232,8 +242,6 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
     const T L = T(-0.75) * flux + T(6) * c.mob * lap;
     const size_t ci = ((size_t)k * ny + j) * nx + i;
     const T dt = c.dt;
-    const T phc = L0[(S_PH + S0) * PLANE];
-    const T ps = phis_cur, ac = acc_cur;
     if (STAGE == CH_RK2_1) {
       A.out[ci] = fma(dt, L, phc);
     } else if (STAGE == CH_RK2_2) {
@@ -257,27 +265,33 @@ __global__ __launch_bounds__(TX* TY) void ch_stage_kernel(ChArgs<T> A) {
   };
 
   // one iteration: stage phi(k+2), the X/Y sums of plane k+1 and the Z sums
-  // of plane k+2, derive mu and F of plane k+1, write plane k (k >= z0)
+  // of plane k+2, derive mu and F of plane k+1, write plane k (k >= z0).
+  // Two barriers: staged planes -> derive, derive -> output.  The next
+  // iteration's staging overwrites the slots of phi(k) and the face sums,
+  // whose last readers (derive, and phi(k) at the own cell, read into a
+  // register) finish before the second barrier; the next derive overwrites
+  // the mu / F slot of plane k-1 only after the next first barrier, which
+  // every wave reaches after its output.
   auto iter = [&](int k, auto sk) {
     constexpr int SK = decltype(sk)::value;  // slot of plane k
     constexpr int S1 = (SK + 1) % 3, S2 = (SK + 2) % 3;
-    commit(S2, S2, true, true, true);
-    if (k + 1 < z1) fetch(k + 3, k + 2, k + 3);  // in flight during this plane's work
+    commit(k + 1, k + 2, S2, S2, true, true, true);
     fetch_pt(k + 1, phis_next, acc_next);
+    if (k + 1 < z1) fetch(k + 3, k + 2, k + 3);  // in flight during this plane's work
     __syncthreads();
     derive(k + 1, std::integral_constant<int, S1>{});
+    const T phc = L0[(S_PH + SK) * PLANE];
     __syncthreads();
-    if (k >= z0 && active) output(k, std::integral_constant<int, SK>{});
+    if (k >= z0 && active) output(k, sk, phc, phis_cur, acc_cur);
     phis_cur = phis_next;
     acc_cur = acc_next;
-    __syncthreads();
   };
 
   // -------- warm-up: phi(z0-2), phi(z0-1) and the Z sums of plane z0-1 ----
   fetch(z0 - 2, -3, z0 - 1);
-  commit(1, 2, true, false, true);
+  commit(-3, z0 - 1, 1, 2, true, false, true);
   fetch(z0 - 1, -3, -3);
-  commit(2, 0, true, false, false);
+  commit(-3, -3, 2, 0, true, false, false);
   fetch(z0, z0 - 1, z0);
   // iterations k = z0-2, z0-1 only stage and derive planes z0-1, z0
   for (int k = z0 - 2; k < z1; k += 3) {

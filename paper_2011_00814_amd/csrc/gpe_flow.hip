@@ -12,9 +12,14 @@
 // result.  Stage 3 updates time level n in place and also writes the face
 // velocity sums u^n + u^{n+1} used for the centre velocity of the CH step.
 //
+// The viscous shear terms use edge fluxes eta_edge (d_a u_b + d_b u_a): each
+// edge of the staggered grid is evaluated once per plane into LDS (3 edge
+// families in 3-D, 1 in 2-D) and every face takes differences of them.
+//
 // The plane loop is unrolled by three with ring slots counted from the tile
-// start, so every LDS address is a compile-time offset from the thread's own
-// position.  The transverse pressure average of the in-plane faces is
+// start, so most LDS addresses are compile-time offsets from the thread's
+// own position (the 2-plane rings of eta, nu and the edge fluxes alternate by
+// plane parity).  The transverse pressure average of the in-plane faces is
 // separable: its per-plane partial sums are carried in registers.  In FP32
 // the next plane's global loads are issued before the current plane's
 // stencil work (software pipelining).
@@ -37,9 +42,12 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
   constexpr int PY = (DIM == 3) ? TY + 3 : 1;  // in-plane Y range [-2, TY]
   constexpr int PLANE = PX * PY;
   constexpr int EY = (DIM == 3) ? PX : 0;     // LDS stride of a +Y step
-  // LDS ring slots (3 planes each) and single-plane buffers
-  constexpr int S_P = 0, S_UX = 3, S_UY = 6, S_UZ = 9, S_PH = 12, S_ET = 15, S_NU = 18;
-  constexpr int S_MU = 21, S_DV = 22, NSLOT = 23;
+  // LDS: 3-plane rings (slot of plane k = (k - z0) mod 3), 2-plane rings
+  // (slot = k & 1) and single-plane buffers
+  constexpr int S_P = 0, S_UX = 3, S_UY = 6, S_UZ = 9, S_PH = 12;
+  constexpr int S_ET = 15, S_NU = 17;    // eta, nu of planes k, k+1
+  constexpr int S_EXZ = 19, S_EYZ = 21;  // edge fluxes between planes k-1|k and k|k+1
+  constexpr int S_MU = 23, S_DV = 24, S_EXY = 25, NSLOT = 26;
   __shared__ T lds[NSLOT * PLANE];
 
   const Grid& g = A.g;
@@ -59,9 +67,11 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
   PlaneMap<T, DIM, PX, PY, NT> pm;
   pm.init(g, x0, y0);
 
-  // ---- plane staging: fetch() issues the global loads of a plane (ghost
-  // rules applied) into registers, commit() writes them and the derived eta
-  // and nu into a ring slot
+  // ---- plane staging: fetch() issues the global loads of plane k into
+  // registers; commit() applies the ghost-rule signs and writes them, with
+  // the derived eta and nu, into a ring slot.  No arithmetic touches a
+  // loaded value before commit(), so the loads stay in flight while the
+  // current plane is processed.
   T r_p[pm.NPASS], r_x[pm.NPASS], r_y[pm.NPASS], r_z[pm.NPASS], r_f[pm.NPASS];
   auto fetch = [&](int k) {
     const ZMap<T> z(g, k);
@@ -78,27 +88,30 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
         r_f[p] = bf[q.oc];
         if (pm.inner_row(p)) {  // p and u are never read on the outermost row
           r_p[p] = bp[q.oc];
-          r_x[p] = bx[q.ox] * (q.sx * z.tan);
-          if (DIM == 3) r_y[p] = by[q.oy] * (q.sy * z.tan);
-          r_z[p] = bz[q.oc] * (q.sz * z.nrm);
+          r_x[p] = bx[q.ox];
+          if (DIM == 3) r_y[p] = by[q.oy];
+          r_z[p] = bz[q.oc];
         }
       }
     }
   };
-  auto commit = [&](int s) {
+  auto commit = [&](int s, int k) {
+    const ZMap<T> z(g, k);
+    T* const e2 = lds + (k & 1) * PLANE;
 #pragma unroll
     for (int p = 0; p < pm.NPASS; ++p) {
       const int lp = (int)threadIdx.x + p * NT;
       if (lp >= PLANE) continue;
+      const auto q = pm.pos(g, p);  // signs (all +1 inside an interior tile)
       const T ph = r_f[p];
       const T eta = eta_of(c, ph);
       lds[(S_P + s) * PLANE + lp] = r_p[p];
-      lds[(S_UX + s) * PLANE + lp] = r_x[p];
-      if (DIM == 3) lds[(S_UY + s) * PLANE + lp] = r_y[p];
-      lds[(S_UZ + s) * PLANE + lp] = r_z[p];
+      lds[(S_UX + s) * PLANE + lp] = r_x[p] * (q.sx * z.tan);
+      if (DIM == 3) lds[(S_UY + s) * PLANE + lp] = r_y[p] * (q.sy * z.tan);
+      lds[(S_UZ + s) * PLANE + lp] = r_z[p] * (q.sz * z.nrm);
       lds[(S_PH + s) * PLANE + lp] = ph;
-      lds[(S_ET + s) * PLANE + lp] = eta;
-      lds[(S_NU + s) * PLANE + lp] = eta * recip(rho_of(c, ph));
+      e2[S_ET * PLANE + lp] = eta;
+      e2[S_NU * PLANE + lp] = eta * recip(rho_of(c, ph));
     }
   };
 
@@ -160,15 +173,55 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
     return T(4) * (P[0] - P[-ea]) + ((P[eb] - P[eb - ea]) + (P[-eb] - P[-eb - ea]));
   };
 
+  // ---- shear edge fluxes (Sec. 3 viscous stencils with the four-cell
+  // average of eta on an edge, kept as the four-cell sum: the face stencils
+  // carry the factor 1/4).  edge_z: edge between planes k and k+1 on the low
+  // face along in-plane axis A (offset ea) of the cell at the pointers'
+  // position: eta4 (d_z u_A + d_A u_Z).  edge_xy: edge at the low-X, low-Y
+  // corner of the cell on plane k: eta4 (d_Y u_X + d_X u_Y).
+  auto edge_z = [&](const T* UA0, const T* UAp, const T* UZp, const T* E0, const T* Ep, int ea) -> T {
+    const T e4 = (E0[0] + Ep[0]) + (E0[-ea] + Ep[-ea]);
+    return e4 * ((UAp[0] - UA0[0]) + (UZp[0] - UZp[-ea]));
+  };
+  auto edge_xy = [&](const T* UX0, const T* UY0, const T* E0) -> T {
+    const T e4 = (E0[0] + E0[-EY]) + (E0[-1] + E0[-1 - EY]);
+    return e4 * ((UX0[0] - UX0[-EY]) + (UY0[0] - UY0[-1]));
+  };
+  // edge fluxes of the Z-directed edges between planes k and k+1 (ring slots
+  // s0, sp of the 3-plane rings) on positions [0, T] of the tile, into the
+  // edge slot of plane k; with the in-plane edges of plane k when xy is set
+  auto edges = [&](int k, int s0, int sp, bool xy) {
+    constexpr int EX_N = TX + 1;
+    constexpr int EN = (DIM == 3) ? (TX + 1) * (TY + 1) : TX + 1;
+    const int e0 = (k & 1) * PLANE, e1 = PLANE - e0;
+    for (int e = (int)threadIdx.x; e < EN; e += NT) {
+      const int ex = e % EX_N, ey = e / EX_N;
+      const int q = ((DIM == 3) ? (ey + 2) * PX : 0) + ex + 2;
+      T* d = lds + q;
+      const T* E0 = d + S_ET * PLANE + e0;
+      const T* Ep = d + S_ET * PLANE + e1;
+      d[S_EXZ * PLANE + e0] = edge_z(d + (S_UX + s0) * PLANE, d + (S_UX + sp) * PLANE, d + (S_UZ + sp) * PLANE, E0, Ep, 1);
+      if (DIM == 3) {
+        d[S_EYZ * PLANE + e0] =
+            edge_z(d + (S_UY + s0) * PLANE, d + (S_UY + sp) * PLANE, d + (S_UZ + sp) * PLANE, E0, Ep, EY);
+        if (xy) d[S_EXY * PLANE] = edge_xy(d + (S_UX + s0) * PLANE, d + (S_UY + s0) * PLANE, E0);
+      }
+    }
+  };
+
   // -------- warm-up: planes z0-2, z0-1, z0 into slots 1, 2, 0 -------------
   // (the ring slot of plane k is (k - z0) mod 3)
   fetch(z0 - 2);
-  commit(1);
+  commit(1, z0 - 2);
   fetch(z0 - 1);
-  commit(2);
+  commit(2, z0 - 1);
   fetch(z0);
-  commit(0);
+  commit(0, z0);
   __syncthreads();
+  edges(z0 - 1, 2, 0, false);  // Z-directed edges between planes z0-1 and z0
+  // eta and nu of the own cell on the previous plane (carried from plane to plane)
+  T eta_prev = L0[S_ET * PLANE + ((z0 - 1) & 1) * PLANE];
+  T nu_prev = L0[S_NU * PLANE + ((z0 - 1) & 1) * PLANE];
   T mu_prev = mu_at(z0 - 1, L0 + (S_PH + 2) * PLANE, L0 + (S_PH + 1) * PLANE, L0 + (S_PH + 0) * PLANE);
   T dv_prev = div_at(z0 - 1, L0 + (S_UX + 2) * PLANE, L0 + (S_UY + 2) * PLANE, L0 + (S_UZ + 2) * PLANE,
                      L0 + (S_UZ + 0) * PLANE);
@@ -180,10 +233,9 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
   }
   if (PREFETCH) fetch(z0 + 1);
 
-  // time level n at the thread's own cell (stages 2 and 3).  FP64 loads it
-  // at the top of the plane's step so that its latency overlaps the mu / div
-  // phase; FP32 (register-capped for occupancy) loads it where it is used.
-  constexpr bool QN_EARLY = sizeof(T) == 8;
+  // time level n at the thread's own cell (stages 2 and 3), loaded at the
+  // top of the plane's step (before the next plane's loads, so that waiting
+  // for it in the update does not also wait for those)
   auto fetch_qn = [&](int k, T* dst) {
     if (STAGE >= 2 && active) {
       const size_t ci = ((size_t)k * ny + j) * nx + i;
@@ -201,10 +253,10 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     __syncthreads();  // readers of slot SP (plane k-2) are done
     if (!PREFETCH) fetch(k + 1);
-    commit(SP);
-    if (PREFETCH && k + 1 < z1) fetch(k + 2);  // in flight during this plane's work
+    commit(SP, k + 1);
     T qn_cur[4] = {T(0), T(0), T(0), T(0)};
-    if (QN_EARLY) fetch_qn(k, qn_cur);
+    fetch_qn(k, qn_cur);
+    if (PREFETCH && k + 1 < z1) fetch(k + 2);  // in flight during this plane's work
     __syncthreads();
 
     // mu and div u of plane k on [-1, T-1] (LDS positions 1 .. T+1)
@@ -220,6 +272,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
                                  b + (S_UZ + S0) * PLANE, b + (S_UZ + SP) * PLANE);
       }
     }
+    edges(k, S0, SP, true);
     // pressure-average partial sums of plane k+1 (own column)
     const T gx_p = prow(L0 + (S_P + SP) * PLANE, 1, EY);
     T gy_p = T(0);
@@ -241,12 +294,15 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       const T* UZp = L0 + (S_UZ + SP) * PLANE;
       const T* PH0 = L0 + (S_PH + S0) * PLANE;
       const T* PHm = L0 + (S_PH + SM) * PLANE;
-      const T* ET0 = L0 + (S_ET + S0) * PLANE;
-      const T* ETm = L0 + (S_ET + SM) * PLANE;
-      const T* ETp = L0 + (S_ET + SP) * PLANE;
-      const T* NU0 = L0 + (S_NU + S0) * PLANE;
-      const T* NUm = L0 + (S_NU + SM) * PLANE;
-      const T* NUp = L0 + (S_NU + SP) * PLANE;
+      const int e0 = (k & 1) * PLANE, e1 = PLANE - e0;  // 2-plane ring slots of k, k+1 (and k-1)
+      const T* ET0 = L0 + S_ET * PLANE + e0;
+      const T* NU0 = L0 + S_NU * PLANE + e0;
+      const T* NUp = L0 + S_NU * PLANE + e1;
+      const T* XZp = L0 + S_EXZ * PLANE + e0;  // edges between planes k and k+1
+      const T* XZm = L0 + S_EXZ * PLANE + e1;  // edges between planes k-1 and k
+      const T* YZp = L0 + S_EYZ * PLANE + e0;
+      const T* YZm = L0 + S_EYZ * PLANE + e1;
+      const T* XY = L0 + S_EXY * PLANE;
       const T* MU = L0 + S_MU * PLANE;
       const T* DV = L0 + S_DV * PLANE;
 
@@ -262,7 +318,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       if (DIM == 3) diff += (nuc + NU0[EY]) * (P0[EY] - pc) - (nuc + NU0[-EY]) * (pc - P0[-EY]);
       {
         const T fp = (nuc + NUp[0]) * (Pp[0] - pc);
-        const T fm = (nuc + NUm[0]) * (pc - Pm[0]);
+        const T fm = (nuc + nu_prev) * (pc - Pm[0]);
         diff += AXI ? (Rk1 * fp - Rk * fm) * inv_rk : fp - fm;
       }
       const T fc = clamp1(PH0[0]);
@@ -271,7 +327,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       // ---- momentum at an in-plane face (normal A with LDS offset ea, other
       // in-plane axis B with offset eb in 3-D, Z transverse) ----
       auto face_inplane = [&](const T* UA0, const T* UAm, const T* UAp, const T* UB0, int ea, int eb,
-                              T gA, T gm, T g0, T gp) -> T {
+                              const T* EZp, const T* EZm, const T* EB, T gA, T gm, T g0, T gp) -> T {
         const T ua = UA0[0];
         const T phc = PH0[0], phl = PH0[-ea];
         const T rho_f = fma(c.rho_hb, fc + clamp1(phl), c.rho_a);  // mean of the two cells
@@ -287,23 +343,11 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
           }
           conv += T(0.25) * tr;
         }
-        // viscous stress divergence with corner-averaged eta, bulk eta_b = eta
+        // viscous stress divergence with edge-averaged eta, bulk eta_b = eta:
+        // normal part, then the shear edge fluxes across Z and across B
         T V = T(2) * (eh * (UA0[ea] - ua) - el * (ua - UA0[-ea]));
-        T Vt;
-        {
-          const T ep = (eh + ETp[0]) + (el + ETp[-ea]);
-          const T em = (eh + ETm[0]) + (el + ETm[-ea]);
-          const T fp = ep * ((UAp[0] - ua) + (UZp[0] - UZp[-ea]));
-          const T fm = em * ((ua - UAm[0]) + (UZ0[0] - UZ0[-ea]));
-          Vt = AXI ? (Rk1 * fp - Rk * fm) * inv_rk : fp - fm;
-        }
-        if (DIM == 3) {
-          const T ep = (eh + ET0[eb]) + (el + ET0[eb - ea]);
-          const T em = (eh + ET0[-eb]) + (el + ET0[-eb - ea]);
-          const T fp = ep * ((UA0[eb] - ua) + (UB0[eb] - UB0[eb - ea]));
-          const T fm = em * ((ua - UA0[-eb]) + (UB0[0] - UB0[-ea]));
-          Vt += fp - fm;
-        }
+        T Vt = AXI ? (Rk1 * EZp[0] - Rk * EZm[0]) * inv_rk : EZp[0] - EZm[0];
+        if (DIM == 3) Vt += EB[eb] - EB[0];
         V += T(0.25) * Vt + (eh * DV[0] - el * DV[-ea]);
         // transversely averaged pressure gradient from the carried partial sums
         const T G = (T(4) * g0 + (gp + gm)) * (DIM == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0));
@@ -312,9 +356,9 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
         return fma(T(-0.5), conv, (-G + V + S + B) * recip(rho_f));
       };
 
-      const T LuX = face_inplane(UX0, UXm, UXp, UY0, 1, EY, c.g[0], gx_m, gx_0, gx_p);
+      const T LuX = face_inplane(UX0, UXm, UXp, UY0, 1, EY, XZp, XZm, XY, c.g[0], gx_m, gx_0, gx_p);
       T LuY = T(0);
-      if (DIM == 3) LuY = face_inplane(UY0, UYm, UYp, UX0, EY, 1, c.g[1], gy_m, gy_0, gy_p);
+      if (DIM == 3) LuY = face_inplane(UY0, UYm, UYp, UX0, EY, 1, YZp, YZm, XY, c.g[1], gy_m, gy_0, gy_p);
 
       // ---- momentum at the Z face between planes k-1 and k ----
       T LuZ = T(0);
@@ -323,7 +367,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
         const T uz = UZ0[0];
         const T phc = PH0[0], phl = PHm[0];
         const T rho_f = fma(c.rho_hb, fc + clamp1(phl), c.rho_a);
-        const T eh = ET0[0], el = ETm[0];
+        const T eh = ET0[0], el = eta_prev;
         T conv = uz * (UZp[0] - UZm[0]);
         {
           const T sx = (UX0[0] + UXm[0]) + (UX0[1] + UXm[1]);
@@ -343,21 +387,8 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
         } else {
           V = T(2) * (eh * (UZp[0] - uz) - el * (uz - UZm[0]));
         }
-        T Vt;
-        {
-          const T ep = (eh + ET0[1]) + (el + ETm[1]);
-          const T em = (eh + ET0[-1]) + (el + ETm[-1]);
-          const T fp = ep * ((UZ0[1] - uz) + (UX0[1] - UXm[1]));
-          const T fm = em * ((uz - UZ0[-1]) + (UX0[0] - UXm[0]));
-          Vt = fp - fm;
-        }
-        if (DIM == 3) {
-          const T ep = (eh + ET0[EY]) + (el + ETm[EY]);
-          const T em = (eh + ET0[-EY]) + (el + ETm[-EY]);
-          const T fp = ep * ((UZ0[EY] - uz) + (UY0[EY] - UYm[EY]));
-          const T fm = em * ((uz - UZ0[-EY]) + (UY0[0] - UYm[0]));
-          Vt += fp - fm;
-        }
+        T Vt = XZm[1] - XZm[0];  // shear edge fluxes between planes k-1 and k
+        if (DIM == 3) Vt += YZm[EY] - YZm[0];
         V += T(0.25) * Vt + (eh * DV[0] - el * dv_prev);
         T G;
         if (DIM == 2) {
@@ -381,7 +412,6 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       T L[4] = {Lp, LuX, LuY, LuZ};
       T out[4];
       T old[4] = {T(0), T(0), T(0), T(0)};
-      if (!QN_EARLY) fetch_qn(k, qn_cur);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if (DIM == 2 && f == 2) continue;
@@ -410,6 +440,8 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
     }
     mu_prev = L0[S_MU * PLANE];
     dv_prev = L0[S_DV * PLANE];
+    eta_prev = L0[S_ET * PLANE + (k & 1) * PLANE];
+    nu_prev = L0[S_NU * PLANE + (k & 1) * PLANE];
 
     gx_m = gx_0;
     gx_0 = gx_p;
