@@ -70,7 +70,9 @@ enum gpe_init_kind {
 typedef struct gpe_params {
   int32_t geometry;        /* gpe_geometry                                             */
   int32_t precision;       /* gpe_precision                                            */
-  int32_t n[3];            /* cells along x, y, z; n[2] = 1 unless 3-D; each >= 3      */
+  int32_t n[3];            /* cells along x, y, z; n[2] = 1 unless 3-D; each >= 3;
+                              total <= 4e9 cells, and one x-row (2-D) or one x-y
+                              plane (3-D) < 2^32 bytes                              */
   int32_t bc[6];           /* gpe_bc of x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; an axis is
                               periodic on both sides or on neither                      */
   int32_t lattice;         /* GPE_D2Q9 in 2-D/axisym; GPE_D3Q15/19/27 in 3-D           */

@@ -98,7 +98,10 @@ int validate(const gpe_params* p) {
   }
   const double ncell = (double)p->n[0] * p->n[1] * p->n[2];
   if (ncell > 4.0e9) return GPE_EINVAL;
-  if ((double)p->n[0] * p->n[1] > 2.0e9) return GPE_EINVAL;
+  // one Z plane (X x Y in the internal axis order) must stay below 2^32 bytes
+  const double esize = p->precision == GPE_FP64 ? 8.0 : 4.0;
+  const double plane = dim == 3 ? (double)p->n[0] * p->n[1] : (double)p->n[0];
+  if (plane * esize >= 4294967296.0) return GPE_EINVAL;
   for (int a = 0; a < dim; ++a) {
     const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
     if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return GPE_EINVAL;

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T>
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
+  const int ij = j * nx + i;  // in-plane offset of the own column
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
   const T* const L0 = lds + own;
 
@@ -72,13 +73,13 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T>
       r_f[p] = r_x[p] = r_y[p] = r_z[p] = T(0);
       if (pm.ok[p]) {
         const auto q = pm.pos(g, p);
-        if (kf >= -2) r_f[p] = bf[q.oc];
+        if (kf >= -2) r_f[p] = at(bf, q.oc);
         if (!pm.inner_row(p)) continue;  // face sums are never read on the outermost row
         if (kxy >= -2) {
-          r_x[p] = bx[q.ox];
-          if (DIM == 3) r_y[p] = by[q.oy];
+          r_x[p] = at(bx, q.ox);
+          if (DIM == 3) r_y[p] = at(by, q.oy);
         }
-        if (kz >= -2) r_z[p] = bz[q.oc];
+        if (kz >= -2) r_z[p] = at(bz, q.oc);
       }
     }
   };
@@ -166,9 +167,9 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T>
   T phis_cur = T(0), acc_cur = T(0), phis_next = T(0), acc_next = T(0);
   auto fetch_pt = [&](int k, T& ps, T& ac) {
     if (active && k >= z0 && k < z1) {
-      const size_t ci = ((size_t)k * ny + j) * nx + i;
-      if (NEED_PHIS) ps = A.phis[ci];
-      if (NEED_ACC) ac = A.acc[ci];
+      const size_t po = (size_t)k * ny * nx;
+      if (NEED_PHIS) ps = at(A.phis + po, ij);
+      if (NEED_ACC) ac = at(A.acc + po, ij);
     }
   };
 
@@ -240,27 +241,29 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T>
     // L = -3 sum_i w_i e_i . F(x + e_i) + 6 M sum_i w_i (mu_i - mu); the
     // stored fluxes carry 4x the centre velocity
     const T L = T(-0.75) * flux + T(6) * c.mob * lap;
-    const size_t ci = ((size_t)k * ny + j) * nx + i;
+    const size_t po = (size_t)k * ny * nx;
+    T& out = at(A.out + po, ij);
+    T& acc = at(A.acc + po, ij);
     const T dt = c.dt;
     if (STAGE == CH_RK2_1) {
-      A.out[ci] = fma(dt, L, phc);
+      out = fma(dt, L, phc);
     } else if (STAGE == CH_RK2_2) {
-      A.out[ci] = ps + T(0.5) * ((phc - ps) + dt * L);
+      out = ps + T(0.5) * ((phc - ps) + dt * L);
     } else if (STAGE == CH_RK4_1) {
       const T kk = dt * L;
-      A.out[ci] = fma(T(0.5), kk, phc);
-      A.acc[ci] = fma(kk, T(1.0 / 6.0), phc);
+      out = fma(T(0.5), kk, phc);
+      acc = fma(kk, T(1.0 / 6.0), phc);
     } else if (STAGE == CH_RK4_2) {
       const T kk = dt * L;
-      A.out[ci] = fma(T(0.5), kk, ps);
-      A.acc[ci] = fma(kk, T(1.0 / 3.0), ac);
+      out = fma(T(0.5), kk, ps);
+      acc = fma(kk, T(1.0 / 3.0), ac);
     } else if (STAGE == CH_RK4_3) {
       const T kk = dt * L;
-      A.out[ci] = ps + kk;
-      A.acc[ci] = fma(kk, T(1.0 / 3.0), ac);
+      out = ps + kk;
+      acc = fma(kk, T(1.0 / 3.0), ac);
     } else {
       const T kk = dt * L;
-      A.out[ci] = fma(kk, T(1.0 / 6.0), ac);
+      out = fma(kk, T(1.0 / 6.0), ac);
     }
   };
 

@@ -142,6 +142,19 @@ __device__ __forceinline__ T eta_of(const Consts<T>& c, T phi) {
   return fma(c.eta_b, clamp1(phi), c.eta_a);
 }
 
+// Element at a 32-bit in-plane offset from a work-group-uniform plane base.
+// Written as base + zero-extended byte offset, so the access uses a scalar
+// 64-bit base and one 32-bit vector offset instead of a per-thread 64-bit
+// address (the library limits a plane to < 2^32 bytes).
+template <typename T>
+__device__ __forceinline__ T& at(T* plane, int off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + (uint32_t)off * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T& at(const T* plane, int off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + (uint32_t)off * (uint32_t)sizeof(T));
+}
+
 // Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }

@@ -20,9 +20,9 @@
 // start, so most LDS addresses are compile-time offsets from the thread's
 // own position (the 2-plane rings of eta, nu and the edge fluxes alternate by
 // plane parity).  The transverse pressure average of the in-plane faces is
-// separable: its per-plane partial sums are carried in registers.  In FP32
-// the next plane's global loads are issued before the current plane's
-// stencil work (software pipelining).
+// separable: its per-plane partial sums are carried in registers.  The next
+// plane's global loads are issued before the current plane's stencil work
+// (software pipelining).
 #include <type_traits>
 
 #include "gpe_plane.hpp"
@@ -36,7 +36,6 @@ struct FlowOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 1; };
 
 template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
 __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowArgs<T> A) {
-  constexpr bool PREFETCH = sizeof(T) == 4;
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 3;                  // in-plane X range [-2, TX]
   constexpr int PY = (DIM == 3) ? TY + 3 : 1;  // in-plane Y range [-2, TY]
@@ -61,6 +60,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
+  const int ij = j * nx + i;  // in-plane offset of the own column
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
   T* const L0 = lds + own;  // LDS base of the thread's own column
 
@@ -85,12 +85,12 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       r_p[p] = r_x[p] = r_y[p] = r_z[p] = r_f[p] = T(0);
       if (pm.ok[p]) {
         const auto q = pm.pos(g, p);
-        r_f[p] = bf[q.oc];
+        r_f[p] = at(bf, q.oc);
         if (pm.inner_row(p)) {  // p and u are never read on the outermost row
-          r_p[p] = bp[q.oc];
-          r_x[p] = bx[q.ox];
-          if (DIM == 3) r_y[p] = by[q.oy];
-          r_z[p] = bz[q.oc];
+          r_p[p] = at(bp, q.oc);
+          r_x[p] = at(bx, q.ox);
+          if (DIM == 3) r_y[p] = at(by, q.oy);
+          r_z[p] = at(bz, q.oc);
         }
       }
     }
@@ -231,14 +231,14 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
     gy_m = prow(L0 + (S_P + 2) * PLANE, EY, 1);
     gy_0 = prow(L0 + (S_P + 0) * PLANE, EY, 1);
   }
-  if (PREFETCH) fetch(z0 + 1);
+  fetch(z0 + 1);
 
   // time level n at the thread's own cell (stages 2 and 3), loaded at the
   // top of the plane's step (before the next plane's loads, so that waiting
   // for it in the update does not also wait for those)
   auto fetch_qn = [&](int k, T* dst) {
     if (STAGE >= 2 && active) {
-      const size_t ci = ((size_t)k * ny + j) * nx + i;
+      const size_t ci = (size_t)k * ny * nx + ij;
 #pragma unroll
       for (int f = 0; f < 4; ++f)
         if (DIM == 3 || f != 2) dst[f] = A.qn[f][ci];
@@ -252,11 +252,10 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
     constexpr int S0 = decltype(slots)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     __syncthreads();  // readers of slot SP (plane k-2) are done
-    if (!PREFETCH) fetch(k + 1);
     commit(SP, k + 1);
     T qn_cur[4] = {T(0), T(0), T(0), T(0)};
     fetch_qn(k, qn_cur);
-    if (PREFETCH && k + 1 < z1) fetch(k + 2);  // in flight during this plane's work
+    if (k + 1 < z1) fetch(k + 2);  // in flight during this plane's work
     __syncthreads();
 
     // mu and div u of plane k on [-1, T-1] (LDS positions 1 .. T+1)
@@ -407,7 +406,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       // ---- Shu-Osher combination of the stage (increment form) ----
       const bool bX = (i == 0 && g.bc[0] != BC_PERIODIC);
       const bool bY = (DIM == 3) && (j == 0 && g.bc[2] != BC_PERIODIC);
-      const size_t ci = ((size_t)k * ny + j) * nx + i;
+      const size_t ci = (size_t)k * ny * nx + ij;
       T q[4] = {P0[0], UX0[0], (DIM == 3) ? UY0[0] : T(0), UZ0[0]};
       T L[4] = {Lp, LuX, LuY, LuZ};
       T out[4];
