@@ -62,8 +62,11 @@ enum gpe_init_kind {
   GPE_INIT_NONE = 0,     /* phi = init_amp everywhere                                  */
   GPE_INIT_DROP = 1,     /* phi = tanh(2 (R - r) / init_width): liquid sphere/disc     */
   GPE_INIT_BUBBLE = 2,   /* phi = tanh(2 (r - R) / init_width): gas sphere/disc        */
-  GPE_INIT_LAYER = 3     /* phi = tanh(2 (y - y0(x)) / init_width) (2-D) or in z (3-D),
+  GPE_INIT_LAYER = 3,    /* phi = tanh(2 (y - y0(x)) / init_width) (2-D) or in z (3-D),
                             y0 = init_center[1 or 2] + init_amp cos(2 pi x_c / nx)     */
+  GPE_INIT_ELLIPSE = 4   /* phi = tanh(2 R (1 - rho) / init_width), R = init_radius,
+                            rho = |((x-x0)/a, (y-y0)/b[, (z-z0)/R])|,
+                            a = R (1 + init_amp), b = R (1 - init_amp), |init_amp| < 1 */
 };
 
 /* Physical and numerical parameters in lattice units (dx = 1). */
@@ -195,6 +198,46 @@ int gpe_set_step_time(gpe_state* s, int64_t step, double t);
  * the number of kernels (<= max) or a negative gpe_error. */
 int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names,
                      double* ms, double* bytes);
+
+/* ------------------------------------------------------------------------
+ * Batched ensemble: many independent 2-D (or many axisymmetric) grids of
+ * different sizes and parameters advanced together, one kernel launch per
+ * time-step stage for the whole batch (the per-stage launches of one step
+ * are replayed as one HIP graph).  Every case runs the same kernels and
+ * arithmetic as a single grid: its state after n steps is bitwise the state
+ * gpe_run_n gives for that case alone.  All cases share one precision and
+ * one geometry (GPE_GEOM_2D or GPE_GEOM_AXISYM); each has its own size,
+ * boundary conditions, dt and material parameters.  The caller owns the
+ * workspace (256-byte aligned) and the stream, as for a single grid.
+ * ------------------------------------------------------------------------ */
+typedef struct gpe_ensemble gpe_ensemble;
+
+/* Workspace bytes for the batch (0 for an invalid batch). */
+size_t gpe_ensemble_workspace_bytes(const gpe_params* cases, int32_t count);
+
+/* Set up `count` cases (1 <= count <= 65536) in d_workspace and initialise
+ * each from its init_kind fields (as gpe_init_state with h_phi0 = NULL).
+ * Returns GPE_EINVAL for an invalid case, a mixed batch or a 3-D case,
+ * GPE_EUNSTABLE if a case without allow_unstable exceeds the stability
+ * estimate, GPE_EWORKSPACE, GPE_EHIP. */
+int gpe_ensemble_create(const gpe_params* cases, int32_t count, void* d_workspace, size_t bytes,
+                        void* hip_stream, gpe_ensemble** out);
+
+/* Advance every case by nsteps time steps (enqueued on the stream). */
+int gpe_ensemble_run_n(gpe_ensemble* e, int64_t nsteps);
+
+/* Per-case finite flag (1: p, u, v, phi all finite; 0 otherwise) into
+ * h_flags[count]; blocks until the stream reaches this point. */
+int gpe_ensemble_finite(gpe_ensemble* e, int32_t* h_flags);
+
+/* Borrowed handle of case i (0 <= i < count) for gpe_diagnostics,
+ * gpe_copy_field, gpe_set_step_time or stepping that case alone; valid until
+ * gpe_ensemble_destroy and never passed to gpe_destroy.  NULL if invalid. */
+gpe_state* gpe_ensemble_case(gpe_ensemble* e, int32_t i);
+
+/* Free the host-side ensemble handle and its case handles (never the
+ * workspace).  NULL is ignored. */
+void gpe_ensemble_destroy(gpe_ensemble* e);
 
 /* Free the host-side handle (never the workspace). NULL is ignored. */
 void gpe_destroy(gpe_state* s);

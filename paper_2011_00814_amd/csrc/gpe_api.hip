@@ -1,4 +1,4 @@
-// gpe_api.cpp -- host side of libgpe: parameter validation and stability
+// gpe_api.hip -- host side of libgpe: parameter validation and stability
 // estimates, workspace layout, the per-step launch sequence, HIP-graph
 // replay, diagnostics and field transfer.  Implements include/gpe.h.
 #include <hip/hip_runtime.h>
@@ -11,6 +11,7 @@
 
 #include "gpe.h"
 #include "gpe_device.hpp"
+#include "gpe_host.hpp"
 #include "gpe_misc.hpp"
 
 namespace {
@@ -19,55 +20,7 @@ using gpe::ChArgs;
 using gpe::Consts;
 using gpe::FlowArgs;
 using gpe::Grid;
-
-// Workspace buffers (internal axis order for velocities: X, Y, Z).
-enum Buf {
-  B_Q0 = 0,   // p, uX, uY, uZ at time level n        (4 slots)
-  B_Q1 = 4,   // first RK stage                       (4 slots)
-  B_Q2 = 8,   // second RK stage                      (4 slots)
-  B_PHI = 12, // phi*
-  B_PHA = 13, // CH stage buffer A
-  B_PHB = 14, // CH stage buffer B (RK4)
-  B_ACC = 15, // RK4 running sum
-  B_US = 16,  // u^n + u^{n+1} on X, Y, Z faces      (3 slots)
-  B_SCR = 19, // reduction scratch
-  B_COUNT = 20
-};
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-}  // namespace
-
-struct gpe_state {
-  gpe_params P;
-  int dim;                 // 2 or 3
-  bool axi;
-  size_t esize;            // bytes per element
-  size_t ncell;
-  Grid grid;               // internal
-  hipStream_t stream;
-  char* ws;
-  size_t ws_bytes;
-  size_t off[B_COUNT];     // byte offsets; SIZE_MAX when absent
-  int64_t step;
-  double t;
-  double mass_abs0;
-  int sticky;
-  hipGraphExec_t graph;
-  bool graph_ok;
-  int ncu;                 // compute units of the device the handle runs on
-};
-
-namespace {
-
-bool has_buf(const gpe_state* s, int b) { return s->off[b] != (size_t)-1; }
-
-template <typename T>
-T* buf(const gpe_state* s, int b) {
-  return has_buf(s, b) ? reinterpret_cast<T*>(s->ws + s->off[b]) : nullptr;
-}
+using namespace gpe_host;
 
 int dim_of(const gpe_params* p) { return p->geometry == GPE_GEOM_3D ? 3 : 2; }
 
@@ -121,7 +74,9 @@ int validate(const gpe_params* p) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->g[a])) return GPE_EINVAL;
   if (!std::isfinite(p->rho_ref)) return GPE_EINVAL;
-  if (p->init_kind < 0 || p->init_kind > 3) return GPE_EINVAL;
+  if (p->init_kind < 0 || p->init_kind > 4) return GPE_EINVAL;
+  if (p->init_kind == GPE_INIT_ELLIPSE && (!(p->init_radius > 0) || !(std::fabs(p->init_amp) < 1.0)))
+    return GPE_EINVAL;
   return GPE_OK;
 }
 
@@ -218,64 +173,45 @@ struct KernelTimer {
   int n = 0;
 };
 
+int flow_zchunk(const gpe_state* s, size_t esize) {
+  if (s->dim == 3)
+    return esize == 8 ? gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, double>::TX, gpe::FlowTile<3, double>::TY,
+                                           gpe::FlowTile<3, double>::BPC, s->ncu)
+                      : gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, float>::TX, gpe::FlowTile<3, float>::TY,
+                                           gpe::FlowTile<3, float>::BPC, s->ncu);
+  return gpe::choose_zchunk(s->grid.n, gpe::FlowTile<2, float>::TX, gpe::FlowTile<2, float>::TY,
+                            gpe::FlowTile<2, float>::BPC, s->ncu);
+}
+
+int ch_zchunk(const gpe_state* s, size_t esize) {
+  if (s->dim == 3)
+    return esize == 8 ? gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, double>::TX, gpe::ChTile<3, double>::TY,
+                                           gpe::ChTile<3, double>::BPC, s->ncu)
+                      : gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, float>::TX, gpe::ChTile<3, float>::TY,
+                                           gpe::ChTile<3, float>::BPC, s->ncu);
+  return gpe::choose_zchunk(s->grid.n, gpe::ChTile<2, float>::TX, gpe::ChTile<2, float>::TY,
+                            gpe::ChTile<2, float>::BPC, s->ncu);
+}
+
 template <typename T>
 hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
   const int geom = s->P.geometry;
-  const Consts<T> c = make_consts<T>(&s->P, s->dim);
   hipError_t e = hipSuccess;
   auto mark = [&]() {
     if (kt) (void)hipEventRecord(kt->ev[kt->n++], s->stream);
   };
   mark();
-  FlowArgs<T> f;
-  f.g = s->grid;
-  f.g.zchunk = (s->dim == 3)
-                   ? gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, T>::TX, gpe::FlowTile<3, T>::TY,
-                                        gpe::FlowTile<3, T>::BPC, s->ncu)
-                   : gpe::choose_zchunk(s->grid.n, gpe::FlowTile<2, T>::TX, gpe::FlowTile<2, T>::TY,
-                                        gpe::FlowTile<2, T>::BPC, s->ncu);
-  f.c = c;
-  f.phi = buf<T>(s, B_PHI);
-  for (int a = 0; a < 3; ++a) f.usum[a] = buf<T>(s, B_US + a);
+  const int zf = flow_zchunk(s, sizeof(T));
   for (int st = 1; st <= 3; ++st) {
-    const int src = st == 1 ? B_Q0 : (st == 2 ? B_Q1 : B_Q2);
-    const int dst = st == 1 ? B_Q1 : (st == 2 ? B_Q2 : B_Q0);
-    for (int q = 0; q < 4; ++q) {
-      f.src[q] = buf<T>(s, src + q);
-      f.qn[q] = buf<T>(s, B_Q0 + q);
-      f.dst[q] = buf<T>(s, dst + q);
-    }
-    e = gpe::launch_flow<T>(f, geom, st, s->stream);
+    e = gpe::launch_flow<T>(flow_args<T>(s, st, zf), geom, st, s->stream);
     mark();
     if (e != hipSuccess) return e;
   }
-  ChArgs<T> h;
-  h.g = s->grid;
-  h.g.zchunk = (s->dim == 3)
-                   ? gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, T>::TX, gpe::ChTile<3, T>::TY,
-                                        gpe::ChTile<3, T>::BPC, s->ncu)
-                   : gpe::choose_zchunk(s->grid.n, gpe::ChTile<2, T>::TX, gpe::ChTile<2, T>::TY,
-                                        gpe::ChTile<2, T>::BPC, s->ncu);
-  h.c = c;
-  for (int a = 0; a < 3; ++a) h.usum[a] = buf<T>(s, B_US + a);
-  T* phi = buf<T>(s, B_PHI);
-  T* pa = buf<T>(s, B_PHA);
-  T* pb = buf<T>(s, B_PHB);
-  T* acc = buf<T>(s, B_ACC);
-  struct Stg { int stage; T* in; T* out; };
-  std::vector<Stg> seq;
-  if (s->dim == 2) {
-    seq = {{gpe::CH_RK2_1, phi, pa}, {gpe::CH_RK2_2, pa, phi}};
-  } else {
-    seq = {{gpe::CH_RK4_1, phi, pa}, {gpe::CH_RK4_2, pa, pb}, {gpe::CH_RK4_3, pb, pa},
-           {gpe::CH_RK4_4, pa, phi}};
-  }
-  for (const Stg& st : seq) {
-    h.phi_in = st.in;
-    h.out = st.out;
-    h.phis = phi;
-    h.acc = acc;
-    e = gpe::launch_ch<T>(h, geom, st.stage, s->stream);
+  ChArgs<T> h[4];
+  int stage[4];
+  const int nch = ch_args<T>(s, ch_zchunk(s, sizeof(T)), h, stage);
+  for (int q = 0; q < nch; ++q) {
+    e = gpe::launch_ch<T>(h[q], geom, stage[q], s->stream);
     mark();
     if (e != hipSuccess) return e;
   }
@@ -380,6 +316,60 @@ int init_fields_t(gpe_state* s, const double* h_phi0, const double* h_p0) {
 }
 
 }  // namespace
+
+namespace gpe_host {
+
+template <typename T>
+FlowArgs<T> flow_args(const gpe_state* s, int st, int zchunk) {
+  FlowArgs<T> f;
+  f.g = s->grid;
+  f.g.zchunk = zchunk;
+  f.c = make_consts<T>(&s->P, s->dim);
+  f.phi = buf<T>(s, B_PHI);
+  for (int a = 0; a < 3; ++a) f.usum[a] = buf<T>(s, B_US + a);
+  const int src = st == 1 ? B_Q0 : (st == 2 ? B_Q1 : B_Q2);
+  const int dst = st == 1 ? B_Q1 : (st == 2 ? B_Q2 : B_Q0);
+  for (int q = 0; q < 4; ++q) {
+    f.src[q] = buf<T>(s, src + q);
+    f.qn[q] = buf<T>(s, B_Q0 + q);
+    f.dst[q] = buf<T>(s, dst + q);
+  }
+  return f;
+}
+
+template <typename T>
+int ch_args(const gpe_state* s, int zchunk, ChArgs<T> a[4], int stage[4]) {
+  ChArgs<T> h;
+  h.g = s->grid;
+  h.g.zchunk = zchunk;
+  h.c = make_consts<T>(&s->P, s->dim);
+  for (int q = 0; q < 3; ++q) h.usum[q] = buf<T>(s, B_US + q);
+  T* phi = buf<T>(s, B_PHI);
+  T* pa = buf<T>(s, B_PHA);
+  T* pb = buf<T>(s, B_PHB);
+  h.phis = phi;
+  h.acc = buf<T>(s, B_ACC);
+  struct Stg { int stage; T* in; T* out; };
+  const Stg rk2[2] = {{gpe::CH_RK2_1, phi, pa}, {gpe::CH_RK2_2, pa, phi}};
+  const Stg rk4[4] = {{gpe::CH_RK4_1, phi, pa}, {gpe::CH_RK4_2, pa, pb}, {gpe::CH_RK4_3, pb, pa},
+                      {gpe::CH_RK4_4, pa, phi}};
+  const int n = s->dim == 2 ? 2 : 4;
+  for (int q = 0; q < n; ++q) {
+    const Stg& t = s->dim == 2 ? rk2[q] : rk4[q];
+    a[q] = h;
+    a[q].phi_in = t.in;
+    a[q].out = t.out;
+    stage[q] = t.stage;
+  }
+  return n;
+}
+
+template FlowArgs<float> flow_args<float>(const gpe_state*, int, int);
+template FlowArgs<double> flow_args<double>(const gpe_state*, int, int);
+template int ch_args<float>(const gpe_state*, int, ChArgs<float>*, int*);
+template int ch_args<double>(const gpe_state*, int, ChArgs<double>*, int*);
+
+}  // namespace gpe_host
 
 extern "C" {
 

@@ -23,8 +23,9 @@ namespace gpe {
 template <typename T>
 struct ChOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 2; };
 
+// One work-group tile (btx, bty) x Z chunk btz of the grid described by A.
 template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T> A) {
+__device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int bty, int btz) {
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 4;                  // in-plane X range [-2, TX+1]
   constexpr int PY = (DIM == 3) ? TY + 4 : 1;
@@ -40,8 +41,6 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T>
   const Consts<T>& c = A.c;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
-  int btx, bty, btz;
-  tile_of_block(g, btx, bty, btz);
   const int x0 = btx * TX, y0 = bty * TY;
   const int z0 = btz * g.zchunk;
   const int z1 = min(z0 + g.zchunk, nz);
@@ -304,6 +303,24 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T>
   }
 }
 
+// Single grid: work-group b runs the tile tile_of_block assigns to it.
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+__global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T> A) {
+  int btx, bty, btz;
+  tile_of_block(A.g, btx, bty, btz);
+  ch_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, btx, bty, btz);
+}
+
+// Batch of grids: work-group b runs tile tiles[b] = (case, btx, bty, btz)
+// with the arguments cases[case].
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+__global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_batch_kernel(const ChArgs<T>* __restrict__ cases,
+                                                                         const int4* __restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const ChArgs<T> A = cases[t.x];
+  ch_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, t.y, t.z, t.w);
+}
+
 template <typename T, int DIM, bool AXI, int STAGE>
 static hipError_t launch_ch_t(const ChArgs<T>& a, hipStream_t s) {
   constexpr int TX = ChTile<DIM, T>::TX, TY = ChTile<DIM, T>::TY;
@@ -335,7 +352,31 @@ hipError_t launch_ch(const ChArgs<T>& a, int geometry, int stage, hipStream_t s)
   return hipErrorInvalidValue;
 }
 
+template <typename T, bool AXI, int STAGE>
+static hipError_t launch_ch_batch_t(const ChArgs<T>* cases, const int4* tiles, int ntiles, hipStream_t s) {
+  constexpr int TX = ChTile<2, T>::TX, TY = ChTile<2, T>::TY;
+  hipLaunchKernelGGL((ch_stage_batch_kernel<T, 2, AXI, STAGE, TX, TY>), dim3((unsigned)ntiles), dim3(TX * TY), 0, s,
+                     cases, tiles);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ch_batch(const ChArgs<T>* cases, const int4* tiles, int ntiles, int geometry, int stage,
+                           hipStream_t s) {
+  if (ntiles < 1) return hipErrorInvalidValue;
+  if (geometry == 0) {
+    if (stage == CH_RK2_1) return launch_ch_batch_t<T, false, CH_RK2_1>(cases, tiles, ntiles, s);
+    if (stage == CH_RK2_2) return launch_ch_batch_t<T, false, CH_RK2_2>(cases, tiles, ntiles, s);
+  } else if (geometry == 1) {
+    if (stage == CH_RK2_1) return launch_ch_batch_t<T, true, CH_RK2_1>(cases, tiles, ntiles, s);
+    if (stage == CH_RK2_2) return launch_ch_batch_t<T, true, CH_RK2_2>(cases, tiles, ntiles, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template hipError_t launch_ch<float>(const ChArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_ch<double>(const ChArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_ch_batch<float>(const ChArgs<float>*, const int4*, int, int, int, hipStream_t);
+template hipError_t launch_ch_batch<double>(const ChArgs<double>*, const int4*, int, int, int, hipStream_t);
 
 }  // namespace gpe

@@ -59,8 +59,8 @@ struct FlowArgs {
   Grid g;
   Consts<T> c;
   const T* src[4];  // stage input (p, uX, uY, uZ)
-  const T* qn[4];   // time level n (read pointwise in stages 2 and 3)
-  T* dst[4];        // stage output; aliases qn in stage 3 (pointwise update)
+  const T* qn[4];   // time level n (read pointwise in stage 2)
+  T* dst[4];        // stage output; in stage 3 also time level n (updated in place)
   const T* phi;     // frozen phase field
   T* usum[3];       // stage 3: u^n + u^{n+1} on each face family
 };
@@ -164,6 +164,15 @@ template <typename T>
 hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, hipStream_t s);
 template <typename T>
 hipError_t launch_ch(const ChArgs<T>& a, int geometry, int stage, hipStream_t s);
+// Batches of 2-D / axisymmetric grids (geometry 0 / 1): one launch runs
+// ntiles work-group tiles, tiles[b] = (case, btx, 0, btz) with the
+// arguments cases[case] (both arrays in device memory).
+template <typename T>
+hipError_t launch_flow_batch(const FlowArgs<T>* cases, const int4* tiles, int ntiles, int geometry, int stage,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_ch_batch(const ChArgs<T>* cases, const int4* tiles, int ntiles, int geometry, int stage,
+                           hipStream_t s);
 
 // Work-group tile shapes (X x Y columns, marched along Z) and the number of
 // work-groups per CU their LDS footprint allows.  FP32 3-D tiles are 32 x 16

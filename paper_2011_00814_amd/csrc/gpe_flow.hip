@@ -34,8 +34,9 @@ namespace gpe {
 template <typename T>
 struct FlowOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 1; };
 
+// One work-group tile (btx, bty) x Z chunk btz of the grid described by A.
 template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowArgs<T> A) {
+__device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, int bty, int btz) {
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 3;                  // in-plane X range [-2, TX]
   constexpr int PY = (DIM == 3) ? TY + 3 : 1;  // in-plane Y range [-2, TY]
@@ -53,8 +54,6 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
   const Consts<T>& c = A.c;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
-  int btx, bty, btz;
-  tile_of_block(g, btx, bty, btz);
   const int x0 = btx * TX, y0 = bty * TY;
   const int z0 = btz * g.zchunk;
   const int z1 = min(z0 + g.zchunk, nz);
@@ -241,7 +240,7 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
       const size_t ci = (size_t)k * ny * nx + ij;
 #pragma unroll
       for (int f = 0; f < 4; ++f)
-        if (DIM == 3 || f != 2) dst[f] = A.qn[f][ci];
+        if (DIM == 3 || f != 2) dst[f] = (STAGE == 3 ? A.dst[f] : A.qn[f])[ci];
     }
   };
 
@@ -455,6 +454,24 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowA
   }
 }
 
+// Single grid: work-group b runs the tile tile_of_block assigns to it.
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+__global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowArgs<T> A) {
+  int btx, bty, btz;
+  tile_of_block(A.g, btx, bty, btz);
+  flow_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, btx, bty, btz);
+}
+
+// Batch of grids: work-group b runs tile tiles[b] = (case, btx, bty, btz)
+// with the arguments cases[case].
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+__global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_batch_kernel(const FlowArgs<T>* __restrict__ cases,
+                                                                         const int4* __restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const FlowArgs<T> A = cases[t.x];
+  flow_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, t.y, t.z, t.w);
+}
+
 template <typename T, int DIM, bool AXI, int STAGE>
 static hipError_t launch_flow_t(const FlowArgs<T>& a, hipStream_t s) {
   constexpr int TX = FlowTile<DIM, T>::TX, TY = FlowTile<DIM, T>::TY;
@@ -487,7 +504,34 @@ hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, hipStream_
   return hipErrorInvalidValue;
 }
 
+template <typename T, bool AXI, int STAGE>
+static hipError_t launch_flow_batch_t(const FlowArgs<T>* cases, const int4* tiles, int ntiles, hipStream_t s) {
+  constexpr int TX = FlowTile<2, T>::TX, TY = FlowTile<2, T>::TY;
+  hipLaunchKernelGGL((flow_stage_batch_kernel<T, 2, AXI, STAGE, TX, TY>), dim3((unsigned)ntiles), dim3(TX * TY), 0,
+                     s, cases, tiles);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_flow_batch(const FlowArgs<T>* cases, const int4* tiles, int ntiles, int geometry, int stage,
+                             hipStream_t s) {
+  if (ntiles < 1) return hipErrorInvalidValue;
+  const bool axi = geometry == 1;
+  if (geometry != 0 && geometry != 1) return hipErrorInvalidValue;
+  switch (stage) {
+    case 1: return axi ? launch_flow_batch_t<T, true, 1>(cases, tiles, ntiles, s)
+                       : launch_flow_batch_t<T, false, 1>(cases, tiles, ntiles, s);
+    case 2: return axi ? launch_flow_batch_t<T, true, 2>(cases, tiles, ntiles, s)
+                       : launch_flow_batch_t<T, false, 2>(cases, tiles, ntiles, s);
+    case 3: return axi ? launch_flow_batch_t<T, true, 3>(cases, tiles, ntiles, s)
+                       : launch_flow_batch_t<T, false, 3>(cases, tiles, ntiles, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template hipError_t launch_flow<float>(const FlowArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_flow<double>(const FlowArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_flow_batch<float>(const FlowArgs<float>*, const int4*, int, int, int, hipStream_t);
+template hipError_t launch_flow_batch<double>(const FlowArgs<double>*, const int4*, int, int, int, hipStream_t);
 
 }  // namespace gpe

@@ -1,0 +1,75 @@
+// gpe_host.hpp -- host-side internals shared by the single-grid API
+// (gpe_api.hip) and the batched ensemble (gpe_ensemble.hip).  Not part of
+// the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "gpe.h"
+#include "gpe_device.hpp"
+
+namespace gpe_host {
+
+// Workspace buffers of one grid (internal axis order for velocities: X, Y, Z).
+enum Buf {
+  B_Q0 = 0,   // p, uX, uY, uZ at time level n        (4 slots)
+  B_Q1 = 4,   // first RK stage                       (4 slots)
+  B_Q2 = 8,   // second RK stage                      (4 slots)
+  B_PHI = 12, // phi*
+  B_PHA = 13, // CH stage buffer A
+  B_PHB = 14, // CH stage buffer B (RK4)
+  B_ACC = 15, // RK4 running sum
+  B_US = 16,  // u^n + u^{n+1} on X, Y, Z faces      (3 slots)
+  B_SCR = 19, // reduction scratch
+  B_COUNT = 20
+};
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace gpe_host
+
+struct gpe_state {
+  gpe_params P;
+  int dim;                 // 2 or 3
+  bool axi;
+  size_t esize;            // bytes per element
+  size_t ncell;
+  gpe::Grid grid;          // internal
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  size_t off[gpe_host::B_COUNT];  // byte offsets; SIZE_MAX when absent
+  int64_t step;
+  double t;
+  double mass_abs0;
+  int sticky;
+  hipGraphExec_t graph;
+  bool graph_ok;
+  int ncu;                 // compute units of the device the handle runs on
+};
+
+namespace gpe_host {
+
+inline bool has_buf(const gpe_state* s, int b) { return s->off[b] != (size_t)-1; }
+
+template <typename T>
+T* buf(const gpe_state* s, int b) {
+  return has_buf(s, b) ? reinterpret_cast<T*>(s->ws + s->off[b]) : nullptr;
+}
+
+// Kernel arguments of flow stage st (1..3) of a grid, with Z chunks of
+// zchunk planes.
+template <typename T>
+gpe::FlowArgs<T> flow_args(const gpe_state* s, int st, int zchunk);
+
+// Kernel arguments of the CH stages of one step (2 in 2-D / axisymmetric,
+// 4 in 3-D) into a[] and their stage ids into stage[]; returns the count.
+template <typename T>
+int ch_args(const gpe_state* s, int zchunk, gpe::ChArgs<T> a[4], int stage[4]);
+
+}  // namespace gpe_host

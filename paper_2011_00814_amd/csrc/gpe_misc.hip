@@ -24,6 +24,20 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
     } else if (a.kind == 3) {
       const double z0 = a.center[2] + a.amp * cos(2.0 * 3.14159265358979323846 * x / a.n[0]);
       ph = tanh(2.0 * (z - z0) / a.width);
+    } else if (a.kind == 4) {
+      // ellipse / ellipsoid: semi-axes R (1 + amp) along x, R (1 - amp) along
+      // the second physical axis (internal Y in 3-D, Z in 2-D), R along z (3-D)
+      const double sa = a.radius * (1.0 + a.amp), sb = a.radius * (1.0 - a.amp);
+      const double ex = (x - a.center[0]) / sa;
+      double rr;
+      if (a.has_y) {
+        const double ey = (y - a.center[1]) / sb, ez = (z - a.center[2]) / a.radius;
+        rr = ex * ex + ey * ey + ez * ez;
+      } else {
+        const double ez = (z - a.center[2]) / sb;
+        rr = ex * ex + ez * ez;
+      }
+      ph = tanh(2.0 * a.radius * (1.0 - sqrt(rr)) / a.width);
     }
     a.phi[c] = T(ph);
     for (int f = 0; f < 4; ++f)

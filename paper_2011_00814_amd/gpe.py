@@ -22,7 +22,7 @@ GPE_GEOM_2D, GPE_GEOM_AXISYM, GPE_GEOM_3D = 0, 1, 2
 GPE_FP64, GPE_FP32 = 0, 1
 GPE_FIELD_P, GPE_FIELD_U, GPE_FIELD_V, GPE_FIELD_W, GPE_FIELD_PHI = 0, 1, 2, 3, 4
 GPE_H2D, GPE_D2H = 0, 1
-GPE_INIT_NONE, GPE_INIT_DROP, GPE_INIT_BUBBLE, GPE_INIT_LAYER = 0, 1, 2, 3
+GPE_INIT_NONE, GPE_INIT_DROP, GPE_INIT_BUBBLE, GPE_INIT_LAYER, GPE_INIT_ELLIPSE = 0, 1, 2, 3, 4
 
 i32, f64 = ctypes.c_int32, ctypes.c_double
 
@@ -67,7 +67,7 @@ _lib = None
 def header_functions():
     """Names of the functions declared in include/gpe.h."""
     src = open(HEADER).read()
-    return re.findall(r"^\s*(?:int|size_t|void|const char\*)\s+(gpe_\w+)\s*\(", src, re.M)
+    return re.findall(r"^\s*(?:int|size_t|void|const char\*|gpe_state\*)\s+(gpe_\w+)\s*\(", src, re.M)
 
 
 def lib():
@@ -105,6 +105,18 @@ def lib():
         L.gpe_destroy.restype = None
         L.gpe_strerror.argtypes = [ctypes.c_int]
         L.gpe_strerror.restype = ctypes.c_char_p
+        L.gpe_ensemble_workspace_bytes.argtypes = [ctypes.POINTER(gpe_params), i32]
+        L.gpe_ensemble_workspace_bytes.restype = sz
+        L.gpe_ensemble_create.argtypes = [ctypes.POINTER(gpe_params), i32, vp, sz, vp, ctypes.POINTER(vp)]
+        L.gpe_ensemble_create.restype = ctypes.c_int
+        L.gpe_ensemble_run_n.argtypes = [vp, ctypes.c_int64]
+        L.gpe_ensemble_run_n.restype = ctypes.c_int
+        L.gpe_ensemble_finite.argtypes = [vp, ctypes.POINTER(i32)]
+        L.gpe_ensemble_finite.restype = ctypes.c_int
+        L.gpe_ensemble_case.argtypes = [vp, i32]
+        L.gpe_ensemble_case.restype = vp
+        L.gpe_ensemble_destroy.argtypes = [vp]
+        L.gpe_ensemble_destroy.restype = None
         _lib = L
     return _lib
 
@@ -192,6 +204,51 @@ def gpe_destroy(h):
     lib().gpe_destroy(h)
 
 
+def _params_array(params_list):
+    arr = (gpe_params * len(params_list))()
+    for q, P in enumerate(params_list):
+        arr[q] = P
+    return arr
+
+
+def gpe_ensemble_workspace_bytes(params_list) -> int:
+    return int(lib().gpe_ensemble_workspace_bytes(_params_array(params_list), len(params_list)))
+
+
+def gpe_ensemble_create(params_list, d_workspace: int, nbytes: int, stream: int):
+    handle = ctypes.c_void_p()
+    rc = lib().gpe_ensemble_create(_params_array(params_list), len(params_list), ctypes.c_void_p(d_workspace),
+                                   nbytes, ctypes.c_void_p(stream), ctypes.byref(handle))
+    if rc:
+        raise GpeError(rc, "gpe_ensemble_create")
+    return handle
+
+
+def gpe_ensemble_run_n(e, n: int):
+    rc = lib().gpe_ensemble_run_n(e, int(n))
+    if rc:
+        raise GpeError(rc, "gpe_ensemble_run_n")
+
+
+def gpe_ensemble_finite(e, count: int) -> np.ndarray:
+    out = (i32 * count)()
+    rc = lib().gpe_ensemble_finite(e, out)
+    if rc:
+        raise GpeError(rc, "gpe_ensemble_finite")
+    return np.array(out[:], dtype=np.int32)
+
+
+def gpe_ensemble_case(e, i: int):
+    h = lib().gpe_ensemble_case(e, int(i))
+    if not h:
+        raise GpeError(GPE_EINVAL, "gpe_ensemble_case")
+    return ctypes.c_void_p(h)
+
+
+def gpe_ensemble_destroy(e):
+    lib().gpe_ensemble_destroy(e)
+
+
 # ---- problem dictionary -> gpe_params ----------------------------------------
 def params_from_problem(prob: dict) -> gpe_params:
     P = gpe_params()
@@ -224,11 +281,38 @@ def params_from_problem(prob: dict) -> gpe_params:
     return P
 
 
-class Solver:
-    """One simulation on one GPU: a torch-allocated workspace, a torch stream
-    and a libgpe handle.  Marshalling only."""
+class _Grid:
+    """Field access and diagnostics of one grid handle (self.h, self.prob,
+    self.shape, self.stream)."""
 
     FIELDS = {"p": GPE_FIELD_P, "u": GPE_FIELD_U, "v": GPE_FIELD_V, "w": GPE_FIELD_W, "phi": GPE_FIELD_PHI}
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def diagnostics(self, check=True) -> dict:
+        return gpe_diagnostics(self.h, check)
+
+    def get(self, key: str) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        gpe_copy_field(self.h, self.FIELDS[key], GPE_D2H, out)
+        return out
+
+    def set(self, key: str, arr):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(self.shape))
+        gpe_copy_field(self.h, self.FIELDS[key], GPE_H2D, a)
+
+    def state(self) -> dict:
+        keys = ("p", "u", "v", "phi") + (("w",) if self.prob["dim"] == 3 else ())
+        st = {k: self.get(k) for k in keys}
+        if self.prob["dim"] != 3:
+            st["w"] = None
+        return st
+
+
+class Solver(_Grid):
+    """One simulation on one GPU: a torch-allocated workspace, a torch stream
+    and a libgpe handle.  Marshalling only."""
 
     def __init__(self, prob: dict, state: dict | None = None, device: str = "cuda:0", stream=None):
         import torch
@@ -262,28 +346,6 @@ class Solver:
     def run(self, n: int):
         gpe_run_n(self.h, n)
 
-    def synchronize(self):
-        self.stream.synchronize()
-
-    def diagnostics(self, check=True) -> dict:
-        return gpe_diagnostics(self.h, check)
-
-    def get(self, key: str) -> np.ndarray:
-        out = np.empty(self.shape, dtype=np.float64)
-        gpe_copy_field(self.h, self.FIELDS[key], GPE_D2H, out)
-        return out
-
-    def set(self, key: str, arr):
-        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(self.shape))
-        gpe_copy_field(self.h, self.FIELDS[key], GPE_H2D, a)
-
-    def state(self) -> dict:
-        keys = ("p", "u", "v", "phi") + (("w",) if self.prob["dim"] == 3 else ())
-        st = {k: self.get(k) for k in keys}
-        if self.prob["dim"] != 3:
-            st["w"] = None
-        return st
-
     def kernel_times(self, nsteps: int):
         return gpe_kernel_times(self.h, nsteps)
 
@@ -291,6 +353,65 @@ class Solver:
         if getattr(self, "h", None) is not None:
             gpe_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EnsembleCase(_Grid):
+    """Borrowed view of one case of an Ensemble (owned by the ensemble)."""
+
+    def __init__(self, ens: "Ensemble", i: int):
+        self.prob = ens.probs[i]
+        self.h = gpe_ensemble_case(ens.e, i)
+        self.stream = ens.stream
+        nx, ny, nz = self.prob["n"]
+        self.shape = (nz, ny, nx)
+
+
+class Ensemble:
+    """A batch of independent 2-D (or axisymmetric) cases advanced together:
+    one torch-allocated workspace, one stream, one libgpe ensemble handle.
+    Marshalling only."""
+
+    def __init__(self, probs: list, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.probs = list(probs)
+        self.params = [params_from_problem(p) for p in self.probs]
+        nbytes = gpe_ensemble_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise GpeError(GPE_EINVAL, "gpe_ensemble_workspace_bytes")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.e = gpe_ensemble_create(self.params, self.ws_ptr, nbytes, self.stream.cuda_stream)
+
+    @property
+    def count(self) -> int:
+        return len(self.probs)
+
+    def run(self, n: int):
+        gpe_ensemble_run_n(self.e, n)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def finite(self) -> np.ndarray:
+        return gpe_ensemble_finite(self.e, self.count)
+
+    def case(self, i: int) -> EnsembleCase:
+        return EnsembleCase(self, i)
+
+    def close(self):
+        if getattr(self, "e", None) is not None:
+            gpe_ensemble_destroy(self.e)
+            self.e = None
 
     def __del__(self):
         try:

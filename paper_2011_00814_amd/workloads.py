@@ -167,3 +167,88 @@ def perturbed(prob, st, seed=0, uamp=1e-3, pamp=1e-4):
             f[tuple(idx)] = 0.0
         out[key] = f
     return out
+
+
+# --------------------------------------------------------------------------
+# Ensemble of independent 2-D drops (input of the batched engine)
+# --------------------------------------------------------------------------
+ENSEMBLE_SIZES = (64, 96, 128, 192, 256)
+ENSEMBLE_ASPECT = 0.2  # semi-axes R (1 + 0.2) along x and R (1 - 0.2) along y
+
+
+def ellipse_phi(prob, R, amp, center=None, W=None):
+    """Elliptic drop: phi = tanh(2 R (1 - rho) / W) with
+    rho = |((x - x0) / a, (y - y0) / b)|, a = R (1 + amp), b = R (1 - amp)."""
+    nx, ny, _ = prob["n"]
+    W = prob["width"] if W is None else W
+    x0, y0 = (nx / 2.0, ny / 2.0) if center is None else center[:2]
+    x, y, _ = _centres(prob)
+    rho = np.sqrt(((x - x0) / (R * (1.0 + amp))) ** 2 + ((y - y0) / (R * (1.0 - amp))) ** 2)
+    return np.tanh(2.0 * R * (1.0 - rho) / W)
+
+
+def recipe_dt(rho_l, rho_g, eta_l, eta_g, mob, W, dim=2):
+    """Time step of the ensemble recipe: 0.8 times the largest step the
+    linear stability estimates allow, capped at 1, with c_s^2 = 1/(3 dt^2).
+
+    With that sound speed the acoustic bound 2 c_s dt / sqrt(3) <= 1 holds at
+    every dt (it equals 2/3), so only two bounds remain:
+      viscous (compressive mode, eigenvalue 3 nu |k|^2 <= 12 nu in 2-D, the
+      TVD-RK3 real-axis limit 2.5127):  dt <= 2.5127 / (3 nu_max 4 dim);
+      Cahn-Hilliard (linearised about phi = +-1, M lam (8a + kappa lam),
+      TVD-RK2 real-axis limit 2), lam = 16/3 the largest eigenvalue of
+      minus the D2Q9 isotropic Laplacian (at wavenumber (pi, pi): the four
+      axis links give 6 * 4 * (1/9) * 2, the diagonals 0), a = 3/(4W),
+      kappa = 3W/8:  dt <= 2 / (M lam (8a + kappa lam))."""
+    nu_max = max(eta_l / rho_l, eta_g / rho_g)
+    dt_visc = 2.5127 / (3.0 * nu_max * 4.0 * dim) if nu_max > 0 else math.inf
+    lam = 16.0 / 3.0
+    a, kappa = 3.0 / (4.0 * W), 3.0 * W / 8.0
+    ch = mob * lam * (8.0 * a + kappa * lam)
+    dt_ch = 2.0 / ch if ch > 0 else math.inf
+    return min(1.0, 0.8 * min(dt_visc, dt_ch))
+
+
+def ensemble_cases(count=512, seed=0, precision="fp32", sizes=ENSEMBLE_SIZES):
+    """`count` independent periodic 2-D elliptic drops (numpy PCG64 seed):
+    N uniform over `sizes`; R ~ U(10, 30) redrawn until 1.2 R + 2 W <= 0.45 N;
+    density ratio exp U(0, ln 100); viscosity ratio exp U(0, ln 50);
+    Laplace number La ~ U(1, 20) (U_c = sigma / eta_L, so Re = We = La on R);
+    Mach 0.05 at dt = 1 (U_c = 0.05 / sqrt(3)), sigma = U_c^2 R / La,
+    eta_L = sigma / U_c; M = 0.05, W = 2; dt from recipe_dt, c_s^2 = 1/(3 dt^2).
+    Returns a list of problem dictionaries whose "init" entry asks for the
+    in-kernel elliptic drop (kind 4, the same profile as ellipse_phi)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W, M = 2.0, 0.05
+    Uc = 0.05 / math.sqrt(3.0)
+    out = []
+    for _ in range(count):
+        N = int(sizes[int(rng.integers(len(sizes)))])
+        while True:
+            R = float(rng.uniform(10.0, 30.0))
+            if 1.2 * R + 2.0 * W <= 0.45 * N:
+                break
+        r_rho = math.exp(rng.uniform(0.0, math.log(100.0)))
+        r_eta = math.exp(rng.uniform(0.0, math.log(50.0)))
+        La = float(rng.uniform(1.0, 20.0))
+        sigma = Uc * Uc * R / La
+        eta_l = sigma / Uc
+        rho_g, eta_g = 1.0 / r_rho, eta_l / r_eta
+        dt = recipe_dt(1.0, rho_g, eta_l, eta_g, M, W)
+        prob = base_problem(
+            dim=2, n=(N, N, 1), bc=(PERIODIC,) * 6, rho_l=1.0, rho_g=rho_g, eta_l=eta_l,
+            eta_g=eta_g, sigma=sigma, mob=M, width=W, dt=dt, cs2=1.0 / (3.0 * dt * dt),
+            precision=precision)
+        prob["init"] = {"kind": 4, "center": (N / 2.0, N / 2.0, 0.0), "radius": R,
+                        "amp": ENSEMBLE_ASPECT, "width": W}
+        prob["meta"] = {"R": R, "r_rho": r_rho, "r_eta": r_eta, "La": La}
+        out.append(prob)
+    return out
+
+
+def ensemble_state(prob) -> dict:
+    """Initial state of an ensemble case as arrays (for the oracle)."""
+    st = zero_state(prob)
+    ini = prob["init"]
+    st["phi"] = ellipse_phi(prob, ini["radius"], ini["amp"], ini["center"], ini["width"])
+    return st
