@@ -4,12 +4,19 @@ Workload: 3-D rising bubble on a 256^3 grid with no-slip walls (density and
 viscosity ratio 10, Eotvos 10, Morton 1e-4, W = 2, M = 0.02, D3Q15 CH
 stencils), FP32.  One step = three TVD-RK3 flow stages + four RK4 CH stages.
 The state is initialised in HBM before the timed region; the timed region is
-K graph-replayed steps between two synchronisations.
+K steps enqueued back to back on the solver's stream with HIP events around
+every kernel, between two synchronisations (the same K steps replayed as HIP
+graphs are timed afterwards for context).
 
 Prints one JSON line: MLUPS (cells x steps / s / 1e6), the roofline of the
-dominant kernel (algorithmic bytes per launch / mean launch time from HIP
-events on the solver's stream, against the 8 TB/s HBM peak), the step-level
-roofline, and the CPU oracle timed on a bounded sample of the same workload.
+dominant kernel (algorithmic bytes per launch / mean launch time from the HIP
+events, against the 8 TB/s HBM peak), the step-level roofline, the CPU oracle
+timed on a bounded sample of the same workload, and a short measurement of
+the batched ensemble (512 independent 2-D drops, 64^2 .. 256^2).
+
+`--workload ensemble` measures the ensemble alone (default 5000 steps):
+aggregate cell updates per second of the batch against the same cases run
+one after another as plain single grids.
 """
 from __future__ import annotations
 
@@ -87,6 +94,71 @@ def cpu_baseline(n: int, precision: str, z_sample: int = 64, steps: int = 1):
     }
 
 
+def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_steps: int = 200) -> dict:
+    """The batched ensemble of 512 seeded 2-D drops: aggregate throughput of
+    `steps` graph-replayed batch steps, per-case finite flags after them, and
+    the time the same cases take one after another as plain single grids.
+    A plain grid's step time depends only on its size (same kernels), so the
+    sequential time is the sum over cases of the step time measured for that
+    case's size (two cases of each size, `baseline_steps` steps each)."""
+    import numpy as np
+    import torch
+
+    from paper_2011_00814_amd import gpe
+    from paper_2011_00814_amd import workloads as W
+
+    cases = W.ensemble_cases(512, seed=0, precision=precision)
+    cells = [c["n"][0] * c["n"][1] for c in cases]
+    ens = gpe.Ensemble(cases, device="cuda:0")
+    ens.run(warmup)
+    ens.synchronize()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(ens.stream)
+    ens.run(steps)
+    b.record(ens.stream)
+    ens.synchronize()
+    ms = a.elapsed_time(b)
+    flags = ens.finite()
+    ens.close()
+    # sequential plain runs, timed per size
+    per_size = {}
+    for N in sorted(set(c["n"][0] for c in cases)):
+        sample = [c for c in cases if c["n"][0] == N][:2]
+        t = []
+        for c in sample:
+            s = gpe.Solver(c, None, device="cuda:0")
+            s.run(5)
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.run(baseline_steps)
+            e1.record(s.stream)
+            s.synchronize()
+            t.append(e0.elapsed_time(e1) / baseline_steps)
+            s.close()
+        per_size[N] = sum(t) / len(t)
+    seq_ms = sum(per_size[c["n"][0]] for c in cases) * steps
+    dts = np.array([c["dt"] for c in cases])
+    agg = sum(cells) * steps / (ms * 1e-3)
+    return {
+        "workload": "512 periodic 2-D elliptic drops, N uniform over {64,96,128,192,256}^2 "
+                    f"({sum(cells)} cells), D2Q9, RK3 flow + RK2 CH, per-case dt, {precision}",
+        "steps": steps,
+        "ms_per_batch_step": round(ms / steps, 4),
+        "aggregate_cell_updates_per_s": round(agg, 1),
+        "aggregate_mlups": round(agg / 1e6, 1),
+        "sequential_ms_per_step_by_size": {str(k): round(v, 5) for k, v in per_size.items()},
+        "sequential_ms_per_batch_step": round(seq_ms / steps, 4),
+        "speedup_vs_sequential": round(seq_ms / ms, 2),
+        "finite_cases": int(flags.sum()),
+        "failed_cases": [int(i) for i in np.nonzero(flags == 0)[0]],
+        "dt": {"min": float(dts.min()), "median": float(np.median(dts)), "max": float(dts.max())},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +167,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("bubble3d", "ensemble"), default="bubble3d")
+    ap.add_argument("--ensemble-steps", type=int, default=200,
+                    help="steps of the ensemble summary in the default line (0: skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -120,6 +195,17 @@ def main():
     from paper_2011_00814_amd import gpe
 
     gpe.lib()  # fails loudly if the HIP library is not built
+    if args.workload == "ensemble":
+        steps = args.steps if "--steps" in sys.argv else 5000
+        r = ensemble_bench(steps, args.warmup, args.precision)
+        print(json.dumps({
+            "metric": "aggregate cell updates/s, batched 2-D ensemble vs sequential single-grid runs",
+            "value": r["aggregate_cell_updates_per_s"], "unit": "cell updates/s", "n_gpus": 1,
+            "steps": steps, "warmup": args.warmup, "ms_per_step": r["ms_per_batch_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": r["workload"]}, "ensemble": r}), flush=True)
+        return
     prob = problem(args.n, args.precision)
     s = gpe.Solver(prob, None, device="cuda:0")
     ncell = args.n ** 3
@@ -208,6 +294,8 @@ def main():
         "diag": {"finite": d["finite"], "steps_run": d["step"],
                  "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass_abs0"]},
     }
+    if args.ensemble_steps > 0:
+        line["ensemble"] = ensemble_bench(args.ensemble_steps, 10, args.precision, baseline_steps=50)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n, args.precision)
     print(json.dumps(line), flush=True)
