@@ -115,17 +115,28 @@ def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_st
     cases = W.ensemble_cases(512, seed=0, precision=precision)
     cells = [c["n"][0] * c["n"][1] for c in cases]
     ens = gpe.Ensemble(cases, device="cuda:0")
+
+    def timed(n):
+        ens.synchronize()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(ens.stream)
+        ens.run(n)
+        b.record(ens.stream)
+        ens.synchronize()
+        return a.elapsed_time(b)
+
     ens.run(warmup)
-    ens.synchronize()
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(ens.stream)
-    ens.run(steps)
-    b.record(ens.stream)
-    ens.synchronize()
-    ms = a.elapsed_time(b)
+    default_ms = timed(min(steps, 100)) / min(steps, 100)  # 32-row tiles
+    rows = ens.autotune(trial_steps=10)
+    tuned_rows = {}
+    for c, r in zip(cases, rows):
+        tuned_rows[str(c["n"][0])] = int(r)
+    ens.run(warmup)
+    ms = timed(steps)
     flags = ens.finite()
+    steps_done = ens.case(0).diagnostics()["step"]
     ens.close()
     # sequential plain runs, timed per size
     per_size = {}
@@ -153,6 +164,9 @@ def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_st
                     f"({sum(cells)} cells), D2Q9, RK3 flow + RK2 CH, per-case dt, {precision}",
         "steps": steps,
         "ms_per_batch_step": round(ms / steps, 4),
+        "ms_per_batch_step_32_row_tiles": round(default_ms, 4),
+        "autotuned_tile_rows_by_size": tuned_rows,
+        "steps_run_per_case": int(steps_done),
         "aggregate_cell_updates_per_s": round(agg, 1),
         "aggregate_mlups": round(agg / 1e6, 1),
         "sequential_ms_per_step_by_size": {str(k): round(v, 5) for k, v in per_size.items()},

@@ -215,8 +215,9 @@ typedef struct gpe_ensemble gpe_ensemble;
 /* Workspace bytes for the batch (0 for an invalid batch). */
 size_t gpe_ensemble_workspace_bytes(const gpe_params* cases, int32_t count);
 
-/* Set up `count` cases (1 <= count <= 65536) in d_workspace and initialise
+/* Set up `count` cases (1 <= count <= 65535) in d_workspace and initialise
  * each from its init_kind fields (as gpe_init_state with h_phi0 = NULL).
+ * Work-group tiles are 32 rows high until gpe_ensemble_autotune.
  * Returns GPE_EINVAL for an invalid case, a mixed batch or a 3-D case,
  * GPE_EUNSTABLE if a case without allow_unstable exceeds the stability
  * estimate, GPE_EWORKSPACE, GPE_EHIP. */
@@ -225,6 +226,16 @@ int gpe_ensemble_create(const gpe_params* cases, int32_t count, void* d_workspac
 
 /* Advance every case by nsteps time steps (enqueued on the stream). */
 int gpe_ensemble_run_n(gpe_ensemble* e, int64_t nsteps);
+
+/* Tile autotuner: for every group of cases with the same number of rows,
+ * try work-group tile heights of 8, 16, 32, 64 and 128 rows (clamped to the
+ * grid) and keep the one with the shortest batch step, timed over
+ * trial_steps graph-replayed steps per candidate (one size group at a time,
+ * the others held fixed).  The trial steps are real steps: every case
+ * advances by them, and results do not depend on the tile height.  h_rows
+ * (NULL or count entries) receives each case's chosen height.  Needs a
+ * non-null stream; blocks until the trials have run. */
+int gpe_ensemble_autotune(gpe_ensemble* e, int32_t trial_steps, int32_t* h_rows);
 
 /* Per-case finite flag (1: p, u, v, phi all finite; 0 otherwise) into
  * h_flags[count]; blocks until the stream reaches this point. */

@@ -31,16 +31,18 @@ using gpe::FlowArgs;
 using namespace gpe_host;
 
 constexpr int kMaxCases = 65535;
-constexpr int kEnsZChunk = 32;   // rows per work-group tile of a case
+constexpr int kEnsZChunk = 32;   // default rows per work-group tile of a case
+constexpr int kMinZChunk = 8;    // smallest tile height (sizes the tile tables)
+constexpr int kTuneRows[] = {8, 16, 32, 64, 128};  // candidates of the autotuner
 constexpr int kFinBlocks = 8;    // work-groups per case of the finite check
 
-int ens_zchunk(int nz) { return nz < kEnsZChunk ? nz : kEnsZChunk; }
+int clamp_rows(int rows, int nz) { return rows < nz ? rows : nz; }
 
 // Byte layout of the workspace of a batch.
 struct Layout {
   size_t flow_args, ch_args, flow_tiles, ch_tiles, flags, fields, ncell, total;
   std::vector<size_t> case_off, case_bytes;
-  int nflow_tiles = 0, nch_tiles = 0;
+  int max_flow_tiles = 0, max_ch_tiles = 0;  // table capacity
 };
 
 template <typename T>
@@ -50,13 +52,13 @@ bool make_layout(const gpe_params* c, int count, Layout& L) {
   long nft = 0, nct = 0;
   for (int i = 0; i < count; ++i) {
     const int nx = c[i].n[0], nz = c[i].n[1];  // internal X, Z of a 2-D grid
-    const long zc = ens_zchunk(nz);
+    const long zc = clamp_rows(kMinZChunk, nz);  // room for the most tiles any tile height gives
     nft += (long)((nx + gpe::FlowTile<2, T>::TX - 1) / gpe::FlowTile<2, T>::TX) * ((nz + zc - 1) / zc);
     nct += (long)((nx + gpe::ChTile<2, T>::TX - 1) / gpe::ChTile<2, T>::TX) * ((nz + zc - 1) / zc);
   }
   if (nft > (1L << 30) || nct > (1L << 30)) return false;
-  L.nflow_tiles = (int)nft;
-  L.nch_tiles = (int)nct;
+  L.max_flow_tiles = (int)nft;
+  L.max_ch_tiles = (int)nct;
   size_t o = 0;
   L.flow_args = o;
   o += align_up(3 * (size_t)count * sizeof(FlowArgs<T>));
@@ -138,6 +140,8 @@ struct gpe_ensemble {
   char* ws;
   std::vector<gpe_state*> cases;
   Layout L;
+  std::vector<int> rows;            // tile height (Z chunk) of every case
+  int nflow_tiles = 0, nch_tiles = 0;  // tiles in the current tables
   hipGraphExec_t graph;
   bool graph_ok;
 };
@@ -151,13 +155,13 @@ hipError_t enqueue_batch_step(gpe_ensemble* e) {
   const int4* ft = reinterpret_cast<const int4*>(e->ws + e->L.flow_tiles);
   const int4* ct = reinterpret_cast<const int4*>(e->ws + e->L.ch_tiles);
   for (int st = 1; st <= 3; ++st) {
-    hipError_t r = gpe::launch_flow_batch<T>(fa + (size_t)(st - 1) * e->count, ft, e->L.nflow_tiles, e->geometry, st,
+    hipError_t r = gpe::launch_flow_batch<T>(fa + (size_t)(st - 1) * e->count, ft, e->nflow_tiles, e->geometry, st,
                                              e->stream);
     if (r != hipSuccess) return r;
   }
   const int stages[2] = {gpe::CH_RK2_1, gpe::CH_RK2_2};
   for (int q = 0; q < 2; ++q) {
-    hipError_t r = gpe::launch_ch_batch<T>(ca + (size_t)q * e->count, ct, e->L.nch_tiles, e->geometry, stages[q],
+    hipError_t r = gpe::launch_ch_batch<T>(ca + (size_t)q * e->count, ct, e->nch_tiles, e->geometry, stages[q],
                                            e->stream);
     if (r != hipSuccess) return r;
   }
@@ -179,7 +183,7 @@ int upload_tables(gpe_ensemble* e) {
   for (int i = 0; i < n; ++i) {
     const gpe_state* s = e->cases[i];
     const int nx = s->grid.n[0], nz = s->grid.n[2];
-    const int zc = ens_zchunk(nz);
+    const int zc = clamp_rows(e->rows[i], nz);
     for (int st = 1; st <= 3; ++st) fa[(size_t)(st - 1) * n + i] = flow_args<T>(s, st, zc);
     ChArgs<T> h[4];
     int stage[4];
@@ -199,7 +203,9 @@ int upload_tables(gpe_ensemble* e) {
     fields[4 * (size_t)i + 3] = buf<T>(s, B_PHI);
     ncell[i] = (int64_t)s->ncell;
   }
-  if ((int)ft.size() != e->L.nflow_tiles || (int)ct.size() != e->L.nch_tiles) return GPE_EINVAL;
+  if ((int)ft.size() > e->L.max_flow_tiles || (int)ct.size() > e->L.max_ch_tiles) return GPE_EINVAL;
+  e->nflow_tiles = (int)ft.size();
+  e->nch_tiles = (int)ct.size();
   ft = xcd_order(ft);
   ct = xcd_order(ct);
   char* w = e->ws;
@@ -267,6 +273,7 @@ int gpe_ensemble_create(const gpe_params* cases, int32_t count, void* d_workspac
     }
     e->cases.push_back(s);
   }
+  e->rows.assign(count, kEnsZChunk);
   r = e->precision == GPE_FP64 ? upload_tables<double>(e) : upload_tables<float>(e);
   if (r) {
     destroy_cases(e);
@@ -302,6 +309,75 @@ int gpe_ensemble_run_n(gpe_ensemble* e, int64_t nsteps) {
     s->step += nsteps;
     s->t = s->step * s->P.dt;
   }
+  return GPE_OK;
+}
+
+int gpe_ensemble_autotune(gpe_ensemble* e, int32_t trial_steps, int32_t* h_rows) {
+  if (!e || trial_steps < 1 || e->stream == nullptr) return GPE_EINVAL;
+  // size classes: cases with the same number of rows (internal Z)
+  std::vector<int> classes;
+  for (gpe_state* s : e->cases) {
+    const int nz = s->grid.n[2];
+    bool seen = false;
+    for (int c : classes) seen = seen || c == nz;
+    if (!seen) classes.push_back(nz);
+  }
+  hipEvent_t t0, t1;
+  if (hipEventCreate(&t0) != hipSuccess) return GPE_EHIP;
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return GPE_EHIP;
+  }
+  int rc = GPE_OK;
+  // time trial_steps batch steps with the current tables (re-uploaded and
+  // re-captured); the steps advance every case
+  auto trial = [&](float& ms) -> int {
+    if (e->graph_ok) (void)hipGraphExecDestroy(e->graph);
+    e->graph_ok = false;
+    int r = e->precision == GPE_FP64 ? upload_tables<double>(e) : upload_tables<float>(e);
+    if (r) return r;
+    r = gpe_ensemble_run_n(e, 1);  // warm the new tiling (eager)
+    if (r) return r;
+    if (hipEventRecord(t0, e->stream) != hipSuccess) return GPE_EHIP;
+    r = gpe_ensemble_run_n(e, trial_steps);
+    if (r) return r;
+    if (hipEventRecord(t1, e->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+        hipEventElapsedTime(&ms, t0, t1) != hipSuccess)
+      return GPE_EHIP;
+    return GPE_OK;
+  };
+  // coordinate search: one size class at a time, the others held fixed
+  for (int nz : classes) {
+    int best_rows = -1;
+    float best = 0.0f;
+    int last = -1;
+    for (int cand : kTuneRows) {
+      const int rows = clamp_rows(cand, nz);
+      if (rows == last) continue;  // candidates beyond the grid height coincide
+      last = rows;
+      for (int i = 0; i < e->count; ++i)
+        if (e->cases[i]->grid.n[2] == nz) e->rows[i] = rows;
+      float ms = 0.0f;
+      rc = trial(ms);
+      if (rc) break;
+      if (best_rows < 0 || ms < best) {
+        best = ms;
+        best_rows = rows;
+      }
+    }
+    if (rc) break;
+    for (int i = 0; i < e->count; ++i)
+      if (e->cases[i]->grid.n[2] == nz) e->rows[i] = best_rows;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc) return rc;
+  if (e->graph_ok) (void)hipGraphExecDestroy(e->graph);
+  e->graph_ok = false;
+  rc = e->precision == GPE_FP64 ? upload_tables<double>(e) : upload_tables<float>(e);
+  if (rc) return rc;
+  if (h_rows)
+    for (int i = 0; i < e->count; ++i) h_rows[i] = e->rows[i];
   return GPE_OK;
 }
 

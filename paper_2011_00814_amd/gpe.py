@@ -111,6 +111,8 @@ def lib():
         L.gpe_ensemble_create.restype = ctypes.c_int
         L.gpe_ensemble_run_n.argtypes = [vp, ctypes.c_int64]
         L.gpe_ensemble_run_n.restype = ctypes.c_int
+        L.gpe_ensemble_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.gpe_ensemble_autotune.restype = ctypes.c_int
         L.gpe_ensemble_finite.argtypes = [vp, ctypes.POINTER(i32)]
         L.gpe_ensemble_finite.restype = ctypes.c_int
         L.gpe_ensemble_case.argtypes = [vp, i32]
@@ -228,6 +230,14 @@ def gpe_ensemble_run_n(e, n: int):
     rc = lib().gpe_ensemble_run_n(e, int(n))
     if rc:
         raise GpeError(rc, "gpe_ensemble_run_n")
+
+
+def gpe_ensemble_autotune(e, trial_steps: int, count: int) -> np.ndarray:
+    rows = (i32 * count)()
+    rc = lib().gpe_ensemble_autotune(e, int(trial_steps), rows)
+    if rc:
+        raise GpeError(rc, "gpe_ensemble_autotune")
+    return np.array(rows[:], dtype=np.int32)
 
 
 def gpe_ensemble_finite(e, count: int) -> np.ndarray:
@@ -404,6 +414,11 @@ class Ensemble:
 
     def finite(self) -> np.ndarray:
         return gpe_ensemble_finite(self.e, self.count)
+
+    def autotune(self, trial_steps: int = 10) -> np.ndarray:
+        """Pick the tile height per grid size (advances every case by the
+        trial steps); returns each case's chosen height."""
+        return gpe_ensemble_autotune(self.e, trial_steps, self.count)
 
     def case(self, i: int) -> EnsembleCase:
         return EnsembleCase(self, i)

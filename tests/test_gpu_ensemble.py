@@ -59,6 +59,29 @@ def test_ensemble_bitwise_equals_single_runs(gpe, precision):
     ens.close()
 
 
+def test_autotuned_tiles_keep_results_bitwise(gpe):
+    cases = _mixed_cases("fp32")
+    ens = gpe.Ensemble(cases)
+    rows = ens.autotune(trial_steps=2)
+    ens.run(5)
+    ens.synchronize()
+    _say(f"[ensemble] autotuned rows {list(rows)}")
+    assert all(r in (8, 16, 32, 64, 128) or r == c["n"][1] for r, c in zip(rows, cases))
+    for i, prob in enumerate(cases):
+        a = ens.case(i)
+        nsteps = a.diagnostics()["step"]
+        s = gpe.Solver(prob, None)
+        s.run(nsteps)
+        s.synchronize()
+        b = s.state()
+        s.close()
+        sa = a.state()
+        for k in sa:
+            if sa[k] is not None:
+                assert np.array_equal(sa[k], b[k]), (i, k, nsteps)
+    ens.close()
+
+
 def test_ellipse_init_matches_recipe_profile(gpe):
     cases = W.ensemble_cases(3, seed=5, precision="fp64")
     ens = gpe.Ensemble(cases)
