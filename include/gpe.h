@@ -184,6 +184,11 @@ int gpe_copy_field(gpe_state* s, int field, int dir, void* host, size_t bytes);
  * precision, layout above), or (size_t)-1 for an invalid field. */
 size_t gpe_field_offset(const gpe_state* s, int field);
 
+/* Device address of a field of the state (layout above; the same address
+ * as the workspace plus gpe_field_offset), or NULL for an invalid field.
+ * For callers that run their own kernels on the fields. */
+void* gpe_field_pointer(const gpe_state* s, int field);
+
 /* Overwrite the step counter and time (checkpoint restart). */
 int gpe_set_step_time(gpe_state* s, int64_t step, double t);
 

@@ -556,6 +556,12 @@ size_t gpe_field_offset(const gpe_state* s, int field) {
   return b < 0 ? (size_t)-1 : s->off[b];
 }
 
+void* gpe_field_pointer(const gpe_state* s, int field) {
+  if (!s) return nullptr;
+  const int b = field_buf(s, field);
+  return b < 0 ? nullptr : (void*)(s->ws + s->off[b]);
+}
+
 int gpe_set_step_time(gpe_state* s, int64_t step, double t) {
   if (!s || step < 0) return GPE_EINVAL;
   s->step = step;

@@ -1,0 +1,561 @@
+// gpe_learn.hip -- kernels of the learned coarse-grid correction
+// (include/gpe_learn.h): restriction of fine states, network input, the
+// three 3 x 3 convolutions forward and backward, loss, Adam, the
+// mass-projected correction and the interface position.
+//
+// The convolutions are direct (per output pixel, all output channels in
+// registers, the layer's weights in LDS as FP32): the network is small
+// (11.7 k weights) and the per-pixel work (<= 9 x 32 x 32 multiply-adds) keeps
+// it far from the memory bound.  Operands are read as bfloat16 or FP32 and
+// every sum accumulates in FP32.  Weight gradients are an im2col product over
+// chunks of 32 pixels staged in LDS; each work-group writes its partial sums
+// and a second pass adds them in a fixed order, so a training step is
+// bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "gpe.h"
+#include "gpe_learn.h"
+
+namespace {
+
+constexpr int C0 = 4, C1 = 32, C2 = 32, C3 = 4;
+constexpr size_t NW1 = (size_t)C1 * 9 * C0, NW2 = (size_t)C2 * 9 * C1, NW3 = (size_t)C3 * 9 * C2;
+constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + NW1, OFF_W2 = OFF_B1 + C1, OFF_B2 = OFF_W2 + NW2;
+constexpr size_t OFF_W3 = OFF_B2 + C2, OFF_B3 = OFF_W3 + NW3, NPARAM = OFF_B3 + C3;
+constexpr int kBlock = 256;
+constexpr int kPixPerBlockW = 2048;  // pixels per work-group of the weight-gradient pass
+constexpr int kMaxPartials = (int)(C2 * 9 * C1 + C2);
+
+// bfloat16 storage: the upper half of the FP32 bit pattern, rounded to
+// nearest even (NaN kept NaN)
+struct bf16 {
+  uint16_t bits;
+};
+__device__ __forceinline__ float to_float(float v) { return v; }
+__device__ __forceinline__ float to_float(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
+__device__ __forceinline__ void store(float& d, float v) { d = v; }
+__device__ __forceinline__ void store(bf16& d, float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) {
+    d.bits = (uint16_t)((u >> 16) | 0x40u);
+    return;
+  }
+  u += 0x7fffu + ((u >> 16) & 1u);
+  d.bits = (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ int wrap(int x, int W) { return x < 0 ? x + W : (x >= W ? x - W : x); }
+
+unsigned blocks_for(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---- restriction ----------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void restrict_kernel(const float* const* fine, float* const* coarse, int B,
+                                                          int ny, int nx, int f) {
+  const int H = ny / f, W = nx / f;
+  const long n = (long)B * H * W;
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int I = (int)(q % W);
+  const long r = q / W;
+  const int J = (int)(r % H);
+  const int b = (int)(r / H);
+  const float* fu = fine[4 * b + 0];
+  const float* fv = fine[4 * b + 1];
+  const float* fp = fine[4 * b + 2];
+  const float* ff = fine[4 * b + 3];
+  float sp = 0.f, sf = 0.f, su = 0.f, sv = 0.f;
+  for (int a = 0; a < f; ++a) {
+    const size_t row = (size_t)(f * J + a) * nx;
+    for (int c = 0; c < f; ++c) {
+      sp += fp[row + f * I + c];
+      sf += ff[row + f * I + c];
+    }
+    su += fu[row + f * I];                         // x-face f*I on fine row f*J + a
+    sv += fv[(size_t)(f * J) * nx + f * I + a];    // y-face f*J on fine column f*I + a
+  }
+  const size_t o = (size_t)J * W + I;
+  coarse[4 * b + 0][o] = su / f;
+  coarse[4 * b + 1][o] = sv / f;
+  coarse[4 * b + 2][o] = sp / (f * f);
+  coarse[4 * b + 3][o] = sf / (f * f);
+}
+
+// ---- network input ----------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(kBlock) void features_kernel(const float* const* fields, int B, int H, int W,
+                                                          float s0, float s1, float s2, float s3, TA* x0) {
+  const long n = (long)B * H * W;
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int x = (int)(q % W);
+  const long r = q / W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  const float* u = fields[4 * b + 0];
+  const float* v = fields[4 * b + 1];
+  const float* p = fields[4 * b + 2];
+  const float* ph = fields[4 * b + 3];
+  const size_t o = (size_t)y * W + x;
+  const float uc = 0.5f * (u[o] + u[(size_t)y * W + wrap(x + 1, W)]);
+  const float vn = (y + 1 < H) ? v[o + W] : 0.f;  // the face above the top row is a wall face
+  const float vc = 0.5f * (v[o] + vn);
+  store(x0[q * 4 + 0], uc / s0);
+  store(x0[q * 4 + 1], vc / s1);
+  store(x0[q * 4 + 2], p[o] / s2);
+  store(x0[q * 4 + 3], ph[o] / s3);
+}
+
+template <typename TA>
+__global__ __launch_bounds__(kBlock) void convert_kernel(const float* src, TA* dst, long n) {
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q < n) store(dst[q], src[q]);
+}
+
+// ---- convolutions -------------------------------------------------------------
+// out[p][o] = bias[o] + sum over taps (dy, dx) and inputs i of
+//   w[o][dy+1][dx+1][i] * x[(y+dy, (x+dx) mod W)][i]   (zero for y+dy outside)
+template <int CI, int CO, typename TA, bool RELU, typename TO>
+__global__ __launch_bounds__(kBlock) void conv_fwd_kernel(const TA* __restrict__ x, const TA* __restrict__ w,
+                                                          const float* __restrict__ bias, TO* __restrict__ y,
+                                                          int B, int H, int W) {
+  __shared__ float sw[CO * 9 * CI];
+  for (int q = threadIdx.x; q < CO * 9 * CI; q += kBlock) sw[q] = to_float(w[q]);
+  __syncthreads();
+  const long P = (long)B * H * W;
+  const long p = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= P) return;
+  const int xx = (int)(p % W);
+  const long r = p / W;
+  const int yy = (int)(r % H);
+  const long b = r / H;
+  float acc[CO];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) acc[o] = bias[o];
+#pragma unroll 1
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int y2 = yy + dy;
+    if (y2 < 0 || y2 >= H) continue;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const TA* in = x + ((b * H + y2) * W + wrap(xx + dx, W)) * CI;
+      float v[CI];
+#pragma unroll
+      for (int i = 0; i < CI; ++i) v[i] = to_float(in[i]);
+      const float* wt = sw + ((dy + 1) * 3 + (dx + 1)) * CI;
+#pragma unroll
+      for (int o = 0; o < CO; ++o) {
+#pragma unroll
+        for (int i = 0; i < CI; ++i) acc[o] = fmaf(wt[o * 9 * CI + i], v[i], acc[o]);
+      }
+    }
+  }
+  TO* out = y + p * CO;
+#pragma unroll
+  for (int o = 0; o < CO; ++o) store(out[o], RELU ? fmaxf(acc[o], 0.f) : acc[o]);
+}
+
+// gin[q][i] = (sum over taps and outputs o of w[o][tap][i] gout[q - tap][o]) *
+//             (ain[q][i] > 0): the gradient w.r.t. the pre-activation of the
+// layer whose ReLU output ain is this layer's input
+template <int CI, int CO, typename TA>
+__global__ __launch_bounds__(kBlock) void conv_bwd_in_kernel(const float* __restrict__ gout,
+                                                             const TA* __restrict__ w, const TA* __restrict__ ain,
+                                                             float* __restrict__ gin, int B, int H, int W) {
+  __shared__ float sw[CO * 9 * CI];
+  for (int q = threadIdx.x; q < CO * 9 * CI; q += kBlock) sw[q] = to_float(w[q]);
+  __syncthreads();
+  const long P = (long)B * H * W;
+  const long p = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= P) return;
+  const int xx = (int)(p % W);
+  const long r = p / W;
+  const int yy = (int)(r % H);
+  const long b = r / H;
+  float acc[CI];
+#pragma unroll
+  for (int i = 0; i < CI; ++i) acc[i] = 0.f;
+#pragma unroll 1
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int yo = yy - dy;  // the output row that read this row through tap dy
+    if (yo < 0 || yo >= H) continue;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const float* g = gout + ((b * H + yo) * W + wrap(xx - dx, W)) * CO;
+      float gv[CO];
+#pragma unroll
+      for (int o = 0; o < CO; ++o) gv[o] = g[o];
+      const float* wt = sw + ((dy + 1) * 3 + (dx + 1)) * CI;
+#pragma unroll
+      for (int o = 0; o < CO; ++o) {
+#pragma unroll
+        for (int i = 0; i < CI; ++i) acc[i] = fmaf(wt[o * 9 * CI + i], gv[o], acc[i]);
+      }
+    }
+  }
+  const TA* a = ain + p * CI;
+  float* out = gin + p * CI;
+#pragma unroll
+  for (int i = 0; i < CI; ++i) out[i] = to_float(a[i]) > 0.f ? acc[i] : 0.f;
+}
+
+// partial[blk][o*9*CI + tap*CI + i] = sum over the block's pixels p of
+//   gout[p][o] * x[p + tap][i];   partial[blk][CO*9*CI + o] = sum gout[p][o]
+template <int CI, int CO, typename TA>
+__global__ __launch_bounds__(kBlock) void conv_bwd_w_kernel(const float* __restrict__ gout,
+                                                            const TA* __restrict__ ain, float* __restrict__ partial,
+                                                            int B, int H, int W) {
+  constexpr int K = 9 * CI;
+  constexpr int E = CO * K;
+  constexpr int NE = (E + kBlock - 1) / kBlock;
+  constexpr int PC = 32;
+  __shared__ float sg[PC][CO];
+  __shared__ float sc[PC][K];
+  float acc[NE];
+#pragma unroll
+  for (int j = 0; j < NE; ++j) acc[j] = 0.f;
+  float bacc = 0.f;
+  const long P = (long)B * H * W;
+  const long p0 = (long)blockIdx.x * kPixPerBlockW;
+  const long p1 = p0 + kPixPerBlockW < P ? p0 + kPixPerBlockW : P;
+  for (long pc = p0; pc < p1; pc += PC) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < PC * CO; q += kBlock) {
+      const long p = pc + q / CO;
+      sg[q / CO][q % CO] = p < p1 ? gout[p * CO + q % CO] : 0.f;
+    }
+    for (int q = threadIdx.x; q < PC * K; q += kBlock) {
+      const int pp = q / K, k = q % K, tap = k / CI, i = k % CI;
+      const long p = pc + pp;
+      float v = 0.f;
+      if (p < p1) {
+        const int xx = (int)(p % W);
+        const long r = p / W;
+        const int yy = (int)(r % H);
+        const long b = r / H;
+        const int y2 = yy + tap / 3 - 1;
+        if (y2 >= 0 && y2 < H) v = to_float(ain[((b * H + y2) * W + wrap(xx + tap % 3 - 1, W)) * CI + i]);
+      }
+      sc[pp][k] = v;
+    }
+    __syncthreads();
+    for (int pp = 0; pp < PC; ++pp) {
+#pragma unroll
+      for (int j = 0; j < NE; ++j) {
+        const int e = (int)threadIdx.x + j * kBlock;
+        if (e < E) acc[j] = fmaf(sg[pp][e / K], sc[pp][e % K], acc[j]);
+      }
+      if ((int)threadIdx.x < CO) bacc += sg[pp][threadIdx.x];
+    }
+  }
+  float* out = partial + (size_t)blockIdx.x * (E + CO);
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    const int e = (int)threadIdx.x + j * kBlock;
+    if (e < E) out[e] = acc[j];
+  }
+  if ((int)threadIdx.x < CO) out[E + threadIdx.x] = bacc;
+}
+
+// grads_w[e] = sum over blocks of partial[blk][e] (blocks in order), and the
+// bias entries likewise
+__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const float* partial, int nblk, int E, int CO,
+                                                                 float* gw, float* gb) {
+  const int e = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (e >= E + CO) return;
+  float s = 0.f;
+  for (int k = 0; k < nblk; ++k) s += partial[(size_t)k * (E + CO) + e];
+  if (e < E)
+    gw[e] = s;
+  else
+    gb[e - E] = s;
+}
+
+// ---- loss ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void loss_kernel(const float* out, const float* t, float* gout, float* partial,
+                                                      long n, float two_over_n) {
+  __shared__ float red[kBlock];
+  float s = 0.f;
+  for (long q = (long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long)gridDim.x * kBlock) {
+    const float d = out[q] - t[q];
+    gout[q] = two_over_n * d;
+    s = fmaf(d, d, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void loss_final_kernel(const float* partial, int nblk, float inv_n, float* loss) {
+  if (threadIdx.x != 0) return;
+  float s = 0.f;
+  for (int k = 0; k < nblk; ++k) s += partial[k];
+  loss[0] = s * inv_n;
+}
+
+// ---- Adam ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void adam_kernel(float* prm, float* m, float* v, const float* g, long n,
+                                                      float lr, float b1, float b2, float eps, float c1, float c2) {
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const float gq = g[q];
+  const float mq = b1 * m[q] + (1.f - b1) * gq;
+  const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  prm[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// ---- correction ---------------------------------------------------------------------
+// sums[b] = sum over the cells of state b of out[.][3]
+__global__ __launch_bounds__(kBlock) void phi_sum_kernel(const float* out, int HW, float* sums) {
+  __shared__ float red[kBlock];
+  const int b = (int)blockIdx.x;
+  float s = 0.f;
+  for (int q = (int)threadIdx.x; q < HW; q += kBlock) s += out[((size_t)b * HW + q) * 4 + 3];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[b] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void apply_kernel(float* const* fields, const float* out, int B, int H, int W,
+                                                       float s0, float s1, float s2, float s3, const float* sums) {
+  const long n = (long)B * H * W;
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int x = (int)(q % W);
+  const long r = q / W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  const size_t o = (size_t)y * W + x;
+  const float* d = out + q * 4;
+  const float mean = sums[b] / (float)(H * W);
+  fields[4 * b + 0][o] += s0 * d[0];
+  if (y > 0) fields[4 * b + 1][o] += s1 * d[1];  // the wall face of row 0 stays 0
+  fields[4 * b + 2][o] += s2 * d[2];
+  fields[4 * b + 3][o] += s3 * (d[3] - mean);
+}
+
+// ---- interface position -----------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void interface_kernel(const float* const* phi, int B, int H, int W,
+                                                           float* out) {
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= (long)B * W) return;
+  const int x = (int)(q % W);
+  const int b = (int)(q / W);
+  const float* c = phi[b];
+  float top = NAN, bot = NAN;
+  for (int j = H - 1; j > 0; --j) {
+    const float a = c[(size_t)(j - 1) * W + x], e = c[(size_t)j * W + x];
+    if ((a > 0.f) != (e > 0.f)) {
+      top = (float)(j - 1) + 0.5f + a / (a - e);
+      break;
+    }
+  }
+  for (int j = 0; j < H - 1; ++j) {
+    const float a = c[(size_t)j * W + x], e = c[(size_t)(j + 1) * W + x];
+    if ((a > 0.f) != (e > 0.f)) {
+      bot = (float)j + 0.5f + a / (a - e);
+      break;
+    }
+  }
+  out[q * 2 + 0] = top;
+  out[q * 2 + 1] = bot;
+}
+
+// ---- launch helpers ----------------------------------------------------------------
+bool dims_ok(int B, int H, int W) { return B >= 1 && H >= 1 && W >= 1 && (long)B * H * W < (1L << 31); }
+
+template <typename TA>
+hipError_t forward_t(const float* prm, const TA* wa, const TA* x0, TA* a1, TA* a2, float* out, int B, int H, int W,
+                     hipStream_t s) {
+  const unsigned g = blocks_for((long)B * H * W);
+  hipLaunchKernelGGL((conv_fwd_kernel<C0, C1, TA, true, TA>), dim3(g), dim3(kBlock), 0, s, x0, wa + OFF_W1,
+                     prm + OFF_B1, a1, B, H, W);
+  hipLaunchKernelGGL((conv_fwd_kernel<C1, C2, TA, true, TA>), dim3(g), dim3(kBlock), 0, s, a1, wa + OFF_W2,
+                     prm + OFF_B2, a2, B, H, W);
+  hipLaunchKernelGGL((conv_fwd_kernel<C2, C3, TA, false, float>), dim3(g), dim3(kBlock), 0, s, a2, wa + OFF_W3,
+                     prm + OFF_B3, out, B, H, W);
+  return hipGetLastError();
+}
+
+size_t gin_floats(int B, int H, int W) { return (size_t)B * H * W * C2; }
+int wblocks(int B, int H, int W) { return (int)(((long)B * H * W + kPixPerBlockW - 1) / kPixPerBlockW); }
+
+template <int CI, int CO, typename TA>
+hipError_t weight_grads(const float* g, const TA* ain, float* partial, float* gw, float* gb, int B, int H, int W,
+                        hipStream_t s) {
+  const int nb = wblocks(B, H, W);
+  hipLaunchKernelGGL((conv_bwd_w_kernel<CI, CO, TA>), dim3(nb), dim3(kBlock), 0, s, g, ain, partial, B, H, W);
+  const int E = CO * 9 * CI;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(E + CO)), dim3(kBlock), 0, s, partial, nb, E, CO, gw,
+                     gb);
+  return hipGetLastError();
+}
+
+template <typename TA>
+hipError_t backward_t(const TA* wa, const TA* x0, const TA* a1, const TA* a2, const float* gout, float* grads,
+                      int B, int H, int W, float* scratch, hipStream_t s) {
+  const size_t ng = gin_floats(B, H, W);
+  float* g2 = scratch;
+  float* g1 = scratch + ng;
+  float* partial = scratch + 2 * ng;
+  const unsigned g = blocks_for((long)B * H * W);
+  hipError_t e = weight_grads<C2, C3, TA>(gout, a2, partial, grads + OFF_W3, grads + OFF_B3, B, H, W, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((conv_bwd_in_kernel<C2, C3, TA>), dim3(g), dim3(kBlock), 0, s, gout, wa + OFF_W3, a2, g2, B, H,
+                     W);
+  e = weight_grads<C1, C2, TA>(g2, a1, partial, grads + OFF_W2, grads + OFF_B2, B, H, W, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((conv_bwd_in_kernel<C1, C2, TA>), dim3(g), dim3(kBlock), 0, s, g2, wa + OFF_W2, a1, g1, B, H,
+                     W);
+  return weight_grads<C0, C1, TA>(g1, x0, partial, grads + OFF_W1, grads + OFF_B1, B, H, W, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gpe_cnn_param_count(void) { return NPARAM; }
+
+size_t gpe_cnn_act_bytes(int32_t act_type) {
+  return act_type == GPE_ACT_BF16 ? 2 : (act_type == GPE_ACT_FP32 ? 4 : 0);
+}
+
+size_t gpe_cnn_scratch_bytes(int32_t B, int32_t H, int32_t W) {
+  if (!dims_ok(B, H, W)) return 0;
+  const size_t parts = (size_t)wblocks(B, H, W) * kMaxPartials;
+  const size_t loss_parts = 1024;
+  return (2 * gin_floats(B, H, W) + parts + loss_parts) * sizeof(float);
+}
+
+int gpe_restrict2d(const float* const* d_fine, float* const* d_coarse, int32_t B, int32_t ny, int32_t nx, int32_t f,
+                   void* stream) {
+  if (!d_fine || !d_coarse || f < 1 || ny % f || nx % f || !dims_ok(B, ny, nx)) return GPE_EINVAL;
+  const long n = (long)B * (ny / f) * (nx / f);
+  hipLaunchKernelGGL(restrict_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, (hipStream_t)stream, d_fine, d_coarse,
+                     B, ny, nx, f);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_features(const float* const* d_fields, int32_t B, int32_t H, int32_t W, const float in_scale[4],
+                     int32_t act_type, void* d_x0, void* stream) {
+  if (!d_fields || !in_scale || !d_x0 || !dims_ok(B, H, W)) return GPE_EINVAL;
+  for (int c = 0; c < 4; ++c)
+    if (!(in_scale[c] > 0.f)) return GPE_EINVAL;
+  const unsigned g = blocks_for((long)B * H * W);
+  hipStream_t s = (hipStream_t)stream;
+  if (act_type == GPE_ACT_BF16)
+    hipLaunchKernelGGL(features_kernel<bf16>, dim3(g), dim3(kBlock), 0, s, d_fields, B, H, W, in_scale[0],
+                       in_scale[1], in_scale[2], in_scale[3], (bf16*)d_x0);
+  else if (act_type == GPE_ACT_FP32)
+    hipLaunchKernelGGL(features_kernel<float>, dim3(g), dim3(kBlock), 0, s, d_fields, B, H, W, in_scale[0],
+                       in_scale[1], in_scale[2], in_scale[3], (float*)d_x0);
+  else
+    return GPE_EINVAL;
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_convert(const float* d_params, void* d_params_act, int32_t act_type, void* stream) {
+  if (!d_params || !d_params_act) return GPE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned g = blocks_for((long)NPARAM);
+  if (act_type == GPE_ACT_BF16)
+    hipLaunchKernelGGL(convert_kernel<bf16>, dim3(g), dim3(kBlock), 0, s, d_params, (bf16*)d_params_act,
+                       (long)NPARAM);
+  else if (act_type == GPE_ACT_FP32)
+    hipLaunchKernelGGL(convert_kernel<float>, dim3(g), dim3(kBlock), 0, s, d_params, (float*)d_params_act,
+                       (long)NPARAM);
+  else
+    return GPE_EINVAL;
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_forward(const float* d_params, const void* d_params_act, const void* d_x0, void* d_a1, void* d_a2,
+                    float* d_out, int32_t B, int32_t H, int32_t W, int32_t act_type, void* stream) {
+  if (!d_params || !d_params_act || !d_x0 || !d_a1 || !d_a2 || !d_out || !dims_ok(B, H, W)) return GPE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (act_type == GPE_ACT_BF16)
+    e = forward_t<bf16>(d_params, (const bf16*)d_params_act, (const bf16*)d_x0, (bf16*)d_a1, (bf16*)d_a2, d_out, B,
+                        H, W, s);
+  else if (act_type == GPE_ACT_FP32)
+    e = forward_t<float>(d_params, (const float*)d_params_act, (const float*)d_x0, (float*)d_a1, (float*)d_a2,
+                         d_out, B, H, W, s);
+  else
+    return GPE_EINVAL;
+  return e == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_loss(const float* d_out, const float* d_target, float* d_gout, float* d_loss, int64_t n,
+                 void* d_scratch, size_t scratch_bytes, void* stream) {
+  if (!d_out || !d_target || !d_gout || !d_loss || !d_scratch || n < 1 || scratch_bytes < 1024 * sizeof(float))
+    return GPE_EINVAL;
+  const int nblk = 1024;
+  hipStream_t s = (hipStream_t)stream;
+  float* partial = (float*)d_scratch;
+  hipLaunchKernelGGL(loss_kernel, dim3(nblk), dim3(kBlock), 0, s, d_out, d_target, d_gout, partial, (long)n,
+                     (float)(2.0 / (double)n));
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, partial, nblk, (float)(1.0 / (double)n), d_loss);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_backward(const float* d_params, const void* d_params_act, const void* d_x0, const void* d_a1,
+                     const void* d_a2, const float* d_gout, float* d_grads, int32_t B, int32_t H, int32_t W,
+                     int32_t act_type, void* d_scratch, size_t scratch_bytes, void* stream) {
+  (void)d_params;
+  if (!d_params_act || !d_x0 || !d_a1 || !d_a2 || !d_gout || !d_grads || !d_scratch || !dims_ok(B, H, W))
+    return GPE_EINVAL;
+  if (scratch_bytes < gpe_cnn_scratch_bytes(B, H, W)) return GPE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (act_type == GPE_ACT_BF16)
+    e = backward_t<bf16>((const bf16*)d_params_act, (const bf16*)d_x0, (const bf16*)d_a1, (const bf16*)d_a2, d_gout,
+                         d_grads, B, H, W, (float*)d_scratch, s);
+  else if (act_type == GPE_ACT_FP32)
+    e = backward_t<float>((const float*)d_params_act, (const float*)d_x0, (const float*)d_a1, (const float*)d_a2,
+                          d_gout, d_grads, B, H, W, (float*)d_scratch, s);
+  else
+    return GPE_EINVAL;
+  return e == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_adam(float* d_params, float* d_m, float* d_v, const float* d_grads, int64_t n, float lr, float beta1,
+                 float beta2, float eps, int64_t t, void* stream) {
+  if (!d_params || !d_m || !d_v || !d_grads || n < 1 || t < 1) return GPE_EINVAL;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, (hipStream_t)stream, d_params, d_m, d_v,
+                     d_grads, (long)n, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_apply(float* const* d_fields, const float* d_out, int32_t B, int32_t H, int32_t W,
+                  const float out_scale[4], float* d_scratch, void* stream) {
+  if (!d_fields || !d_out || !out_scale || !d_scratch || !dims_ok(B, H, W)) return GPE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(phi_sum_kernel, dim3(B), dim3(kBlock), 0, s, d_out, H * W, d_scratch);
+  hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
+                     out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)d_scratch);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_interface_position(const float* const* d_phi, int32_t B, int32_t H, int32_t W, float* d_out,
+                           void* stream) {
+  if (!d_phi || !d_out || !dims_ok(B, H, W)) return GPE_EINVAL;
+  hipLaunchKernelGGL(interface_kernel, dim3(blocks_for((long)B * W)), dim3(kBlock), 0, (hipStream_t)stream, d_phi, B,
+                     H, W, d_out);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+}  // extern "C"

@@ -67,7 +67,7 @@ _lib = None
 def header_functions():
     """Names of the functions declared in include/gpe.h."""
     src = open(HEADER).read()
-    return re.findall(r"^\s*(?:int|size_t|void|const char\*|gpe_state\*)\s+(gpe_\w+)\s*\(", src, re.M)
+    return re.findall(r"^\s*(?:int|size_t|void|void\*|const char\*|gpe_state\*)\s+(gpe_\w+)\s*\(", src, re.M)
 
 
 def lib():
@@ -96,6 +96,8 @@ def lib():
         L.gpe_copy_field.restype = ctypes.c_int
         L.gpe_field_offset.argtypes = [vp, ctypes.c_int]
         L.gpe_field_offset.restype = sz
+        L.gpe_field_pointer.argtypes = [vp, ctypes.c_int]
+        L.gpe_field_pointer.restype = vp
         L.gpe_set_step_time.argtypes = [vp, ctypes.c_int64, f64]
         L.gpe_set_step_time.restype = ctypes.c_int
         L.gpe_kernel_times.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
@@ -184,6 +186,13 @@ def gpe_copy_field(h, field: int, direction: int, host: np.ndarray):
 
 def gpe_field_offset(h, field: int) -> int:
     return int(lib().gpe_field_offset(h, int(field)))
+
+
+def gpe_field_pointer(h, field: int) -> int:
+    p = lib().gpe_field_pointer(h, int(field))
+    if not p:
+        raise GpeError(GPE_EINVAL, "gpe_field_pointer")
+    return int(p)
 
 
 def gpe_set_step_time(h, step: int, t: float):
