@@ -55,9 +55,15 @@ size_t gpe_cnn_scratch_bytes(int32_t B, int32_t H, int32_t W);
 
 /* Restriction of B fine states (ny x nx) to (ny/f) x (nx/f): cell means of
  * p and phi over f x f cells; the coarse low x-face velocity is the mean of
- * the f fine x-faces on it (likewise y).  ny, nx multiples of f. */
+ * the f fine x-faces on it (likewise y).  ny, nx multiples of f; f = 1
+ * copies the states. */
 int gpe_restrict2d(const float* const* d_fine, float* const* d_coarse, int32_t B, int32_t ny, int32_t nx,
                    int32_t f, void* stream);
+
+/* Training target [B][H][W][4] (FP32): (next - pred) / out_scale per field
+ * (u, v, p, phi) and cell, from two tables of B states each. */
+int gpe_cnn_target(const float* const* d_next, const float* const* d_pred, int32_t B, int32_t H, int32_t W,
+                   const float out_scale[4], float* d_target, void* stream);
 
 /* Network input x0 [B][H][W][4] (act_type) from B coarse states. */
 int gpe_cnn_features(const float* const* d_fields, int32_t B, int32_t H, int32_t W, const float in_scale[4],

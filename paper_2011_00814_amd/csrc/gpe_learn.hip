@@ -108,6 +108,19 @@ __global__ __launch_bounds__(kBlock) void features_kernel(const float* const* fi
   store(x0[q * 4 + 3], ph[o] / s3);
 }
 
+__global__ __launch_bounds__(kBlock) void target_kernel(const float* const* next, const float* const* pred, int B,
+                                                        int H, int W, float s0, float s1, float s2, float s3,
+                                                        float* target) {
+  const long n = (long)B * H * W;
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int b = (int)(q / ((long)H * W));
+  const size_t o = (size_t)(q - (long)b * H * W);
+  const float sc[4] = {s0, s1, s2, s3};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) target[q * 4 + c] = (next[4 * b + c][o] - pred[4 * b + c][o]) / sc[c];
+}
+
 template <typename TA>
 __global__ __launch_bounds__(kBlock) void convert_kernel(const float* src, TA* dst, long n) {
   const long q = (long)blockIdx.x * kBlock + threadIdx.x;
@@ -445,6 +458,16 @@ int gpe_restrict2d(const float* const* d_fine, float* const* d_coarse, int32_t B
   const long n = (long)B * (ny / f) * (nx / f);
   hipLaunchKernelGGL(restrict_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, (hipStream_t)stream, d_fine, d_coarse,
                      B, ny, nx, f);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+int gpe_cnn_target(const float* const* d_next, const float* const* d_pred, int32_t B, int32_t H, int32_t W,
+                   const float out_scale[4], float* d_target, void* stream) {
+  if (!d_next || !d_pred || !out_scale || !d_target || !dims_ok(B, H, W)) return GPE_EINVAL;
+  for (int c = 0; c < 4; ++c)
+    if (!(out_scale[c] > 0.f)) return GPE_EINVAL;
+  hipLaunchKernelGGL(target_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, (hipStream_t)stream, d_next,
+                     d_pred, B, H, W, out_scale[0], out_scale[1], out_scale[2], out_scale[3], d_target);
   return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
 }
 

@@ -36,6 +36,7 @@ def lib():
             "gpe_cnn_act_bytes": ([i32], sz),
             "gpe_cnn_scratch_bytes": ([i32, i32, i32], sz),
             "gpe_restrict2d": ([vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
+            "gpe_cnn_target": ([vp, vp, i32, i32, i32, f4, vp, vp], ctypes.c_int),
             "gpe_cnn_features": ([vp, i32, i32, i32, f4, i32, vp, vp], ctypes.c_int),
             "gpe_cnn_convert": ([vp, vp, i32, vp], ctypes.c_int),
             "gpe_cnn_forward": ([vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
@@ -81,6 +82,11 @@ def gpe_cnn_scratch_bytes(B: int, H: int, W: int) -> int:
 
 def gpe_restrict2d(fine_table, coarse_table, B, ny, nx, f, stream):
     _check(lib().gpe_restrict2d(_vp(fine_table), _vp(coarse_table), B, ny, nx, f, _vp(stream)), "gpe_restrict2d")
+
+
+def gpe_cnn_target(next_table, pred_table, B, H, W, out_scale, target, stream):
+    _check(lib().gpe_cnn_target(_vp(next_table), _vp(pred_table), B, H, W, _f4(out_scale), _vp(target), _vp(stream)),
+           "gpe_cnn_target")
 
 
 def gpe_cnn_features(table, B, H, W, in_scale, act_type, x0, stream):

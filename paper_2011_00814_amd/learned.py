@@ -1,0 +1,338 @@
+"""Learned coarse-grid correction on one GPU: training data from the solver's
+own fine runs, training, and the judgement against the fine solver.
+
+Orchestration only.  The fine and coarse runs are batched ensembles
+(gpe_ensemble_*), restriction, targets, the network, its training and the
+interface position are the kernels of include/gpe_learn.h; PyTorch provides
+device buffers, pointer tables and the stream.
+
+Set-up (multi-mode Rayleigh-Taylor, workloads.rt_multimode): a fine grid
+nx x ny and the grid coarser by `factor` with the same physics in its own
+lattice units, so one coarse step spans `factor` fine steps.  A training
+pair is (R s(t), R s(t + factor)) for snapshots of the fine runs, R the
+restriction; the network sees the coarse solver's step from R s(t) and
+learns the difference to R s(t + factor).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import gpe as G
+from . import learn as Lr
+from . import workloads as W
+
+FIELDS = ("u", "v", "p", "phi")
+
+
+class StateStore:
+    """N coarse FP32 states (u, v, p, phi) of H x W cells in one device tensor."""
+
+    def __init__(self, N, H, W_, device):
+        import torch
+
+        self.t = torch.zeros((N, 4, H, W_), dtype=torch.float32, device=device)
+        self.N, self.H, self.W = N, H, W_
+
+    def ptrs(self, idx):
+        base = self.t.data_ptr()
+        step = self.H * self.W * 4
+        return [base + (int(i) * 4 + c) * step for i in idx for c in range(4)]
+
+    def host(self, idx):
+        return self.t[list(idx)].cpu().numpy()
+
+
+def _table(ptrs, device, sync=True):
+    """Device pointer table (written on torch's current stream; with sync,
+    complete before any other stream reads it)."""
+    import torch
+
+    t = Lr.pointer_table(ptrs, device)
+    if sync:
+        torch.cuda.current_stream(t.device).synchronize()
+    return t
+
+
+def _fine_and_coarse(seeds, nx, ny, factor):
+    fine, coarse, phis = [], [], []
+    for s in seeds:
+        pf, st = W.rt_multimode(s, nx, ny, 1)
+        pc, _ = W.rt_multimode(s, nx, ny, factor)
+        fine.append(pf)
+        coarse.append(pc)
+        phis.append(st["phi"])
+    return fine, coarse, phis
+
+
+def _make_fine_ensemble(fine, phis, device):
+    ens = G.Ensemble(fine, device=device)
+    for b, phi in enumerate(phis):
+        ens.case(b).set("phi", phi)
+    ens.synchronize()
+    return ens
+
+
+def generate(seeds, fine_steps, n_snap, factor=4, nx=256, ny=1024, device="cuda:0", log=print):
+    """Fine runs of `seeds`, restricted snapshot pairs and the coarse solver's
+    one-step predictions.  Returns a dict with StateStores X0, X1, S (pairs
+    and predictions, index k * B + b for snapshot k of case b), the coarse
+    problems and timings."""
+    import torch
+
+    B = len(seeds)
+    H, Wc = ny // factor, nx // factor
+    fine, coarse, phis = _fine_and_coarse(seeds, nx, ny, factor)
+    ens = _make_fine_ensemble(fine, phis, device)
+    sid = ens.stream.cuda_stream
+    ftab = _table(Lr.state_pointers([ens.case(b) for b in range(B)]), device)
+    X0 = StateStore(n_snap * B, H, Wc, device)
+    X1 = StateStore(n_snap * B, H, Wc, device)
+    S = StateStore(n_snap * B, H, Wc, device)
+    torch.cuda.synchronize()
+    # snapshot times spread over the run (the last pair ends at fine_steps)
+    times = [int(round(k * (fine_steps - factor) / max(n_snap - 1, 1))) for k in range(n_snap)]
+    tabs = []
+    t0 = time.perf_counter()
+    t = 0
+    for k, tk in enumerate(times):
+        ens.run(tk - t)
+        t = tk
+        d0 = _table(X0.ptrs(range(k * B, (k + 1) * B)), device)
+        Lr.gpe_restrict2d(ftab.data_ptr(), d0.data_ptr(), B, ny, nx, factor, sid)
+        ens.run(factor)
+        t += factor
+        d1 = _table(X1.ptrs(range(k * B, (k + 1) * B)), device)
+        Lr.gpe_restrict2d(ftab.data_ptr(), d1.data_ptr(), B, ny, nx, factor, sid)
+        tabs.append((d0, d1))
+    ens.synchronize()
+    fine_s = time.perf_counter() - t0
+    flags = ens.finite()
+    ens.close()
+    # the coarse solver's step from every X0
+    cens = G.Ensemble(coarse, device=device)
+    csid = cens.stream.cuda_stream
+    ctab = _table(Lr.state_pointers([cens.case(b) for b in range(B)]), device)
+    torch.cuda.synchronize()
+    # the tables are read on the ensemble's stream: they stay referenced
+    # until that stream has run (torch only tracks its current stream)
+    for k in range(n_snap):
+        src = _table(X0.ptrs(range(k * B, (k + 1) * B)), device)
+        dst = _table(S.ptrs(range(k * B, (k + 1) * B)), device)
+        Lr.gpe_restrict2d(src.data_ptr(), ctab.data_ptr(), B, H, Wc, 1, csid)  # copy in
+        cens.run(1)
+        Lr.gpe_restrict2d(ctab.data_ptr(), dst.data_ptr(), B, H, Wc, 1, csid)  # copy out
+        tabs.append((src, dst))
+    cens.synchronize()
+    cens.close()
+    log(f"[learned] generated {n_snap * B} pairs from {B} fine runs x {fine_steps} steps in {fine_s:.1f} s "
+        f"(finite {int(flags.sum())}/{B})")
+    return {"X0": X0, "X1": X1, "S": S, "coarse": coarse, "B": B, "n_snap": n_snap, "H": H, "W": Wc,
+            "fine_seconds": fine_s, "finite": flags}
+
+
+def scales(data, sample=64, seed=0):
+    """Input and output scales per channel (u, v, p, phi) from a sample of
+    the data: RMS of the coarse states (velocities and pressure; phi is
+    O(1)) and RMS of the one-step differences X1 - S."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N = data["X0"].N
+    idx = sorted(rng.choice(N, size=min(sample, N), replace=False).tolist())
+    s = data["S"].host(idx).astype(np.float64)
+    x1 = data["X1"].host(idx).astype(np.float64)
+    rms_state = np.sqrt(np.mean(s ** 2, axis=(0, 2, 3)))
+    rms_diff = np.sqrt(np.mean((x1 - s) ** 2, axis=(0, 2, 3)))
+    in_scale = [max(rms_state[0], rms_state[1], 1e-8)] * 2 + [max(rms_state[2], 1e-10), 1.0]
+    out_scale = [max(v, 1e-12) for v in rms_diff]
+    return [float(v) for v in in_scale], [float(v) for v in out_scale]
+
+
+def _init_params(seed):
+    """He-uniform weights, zero biases, the last layer scaled by 0.1
+    (packed like gpe_cnn_param_count)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for layer in range(3):
+        ci, co = Lr.CHANNELS[layer], Lr.CHANNELS[layer + 1]
+        lim = math.sqrt(6.0 / (9 * ci))
+        w = rng.uniform(-lim, lim, size=(co, 3, 3, ci))
+        if layer == 2:
+            w = w * 0.1
+        parts += [w.ravel(), np.zeros(co)]
+    return np.concatenate(parts)
+
+
+def train(data, iters=2000, batch=16, lr=2e-3, seed=0, act_type=Lr.GPE_ACT_BF16, device="cuda:0", log=print):
+    """Adam on random minibatches of pairs; lr halves every iters/4 steps.
+    Returns (network, loss history, in_scale, out_scale)."""
+    import torch
+
+    in_scale, out_scale = scales(data, seed=seed)
+    H, Wc = data["H"], data["W"]
+    net = Lr.CNN(batch, H, Wc, act_type=act_type, device=device, params=_init_params(seed))
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    N = data["X0"].N
+    hist = []  # (iteration, mean loss over the window ending there)
+    window = []
+    every = max(iters // 20, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iters):
+        idx = rng.choice(N, size=batch, replace=False)
+        # the network runs on torch's current stream: the tables need no sync
+        ts = _table(data["S"].ptrs(idx), device, sync=False)
+        tx = _table(data["X1"].ptrs(idx), device, sync=False)
+        Lr.gpe_cnn_target(tx.data_ptr(), ts.data_ptr(), batch, H, Wc, out_scale, net.target.data_ptr(), net.sid)
+        net.features(ts, batch, in_scale)
+        net.forward(batch)
+        net.loss(batch)
+        net.backward(batch)
+        net.adam(lr=lr * 0.5 ** (4 * it // max(iters, 1)))
+        if it % 5 == 0:
+            window.append(float(net.loss_buf.item()))
+        if (it + 1) % every == 0 or it == iters - 1:
+            hist.append((it, float(np.mean(window)) if window else float("nan")))
+            window = []
+    net.synchronize()
+    secs = time.perf_counter() - t0
+    log(f"[learned] trained {iters} iterations (batch {batch}) in {secs:.1f} s; loss {hist[0][1]:.4g} -> "
+        f"{hist[-1][1]:.4g}")
+    return net, hist, in_scale, out_scale, secs
+
+
+def one_step_gain(net, data, in_scale, out_scale, device="cuda:0", batch=None):
+    """Mean squared one-step error of the coarse solver against the
+    restricted fine solution (in units of out_scale), without and with the
+    network correction, over all pairs of `data`."""
+    import torch
+
+    H, Wc = data["H"], data["W"]
+    batch = batch or net.B
+    N = data["X0"].N
+    tot_plain = tot_net = 0.0
+    cnt = 0
+    zero = torch.zeros_like(net.out)
+    for s in range(0, N, batch):
+        idx = list(range(s, min(s + batch, N)))
+        b = len(idx)
+        ts = _table(data["S"].ptrs(idx), device, sync=False)
+        tx = _table(data["X1"].ptrs(idx), device, sync=False)
+        Lr.gpe_cnn_target(tx.data_ptr(), ts.data_ptr(), b, H, Wc, out_scale, net.target.data_ptr(), net.sid)
+        # without the network: the loss of a zero output
+        net.out.copy_(zero)
+        net.loss(b)
+        plain = float(net.loss_buf.item())
+        net.features(ts, b, in_scale)
+        net.forward(b)
+        net.loss(b)
+        corr = float(net.loss_buf.item())
+        tot_plain += plain * b
+        tot_net += corr * b
+        cnt += b
+    return tot_plain / cnt, tot_net / cnt
+
+
+def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1024, device="cuda:0",
+             log=print):
+    """Fine runs of `seeds` against coarse runs from their restricted
+    initial states, without and with the network (one correction per
+    coarse step), fine_steps / factor coarse steps.  Interface positions
+    (outermost phi = 0 crossings per column, top and bottom) are compared
+    on the coarse grid, the fine solution restricted to it; errors are in
+    coarse cells (factor fine cells).  A coarse case that is not finite at
+    the end falls back to the fine run."""
+    import torch
+
+    B = len(seeds)
+    H, Wc = ny // factor, nx // factor
+    csteps = fine_steps // factor
+    fine, coarse, phis = _fine_and_coarse(seeds, nx, ny, factor)
+    ens_f = _make_fine_ensemble(fine, phis, device)
+    ens_c = G.Ensemble(coarse, device=device)
+    ens_n = G.Ensemble(coarse, device=device, stream=ens_c.stream)
+    sid = ens_c.stream.cuda_stream
+    ftab = _table(Lr.state_pointers([ens_f.case(b) for b in range(B)]), device)
+    ctab = _table(Lr.state_pointers([ens_c.case(b) for b in range(B)]), device)
+    ntab = _table(Lr.state_pointers([ens_n.case(b) for b in range(B)]), device)
+    phi_ptrs = lambda tab_ptrs: [tab_ptrs[4 * b + 3] for b in range(B)]  # noqa: E731
+    torch.cuda.synchronize()
+    ens_f.synchronize()
+    Lr.gpe_restrict2d(ftab.data_ptr(), ctab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
+    Lr.gpe_restrict2d(ftab.data_ptr(), ntab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
+    ens_f.synchronize()
+    # fine reference (timed)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ens_f.stream)
+    ens_f.run(fine_steps)
+    e1.record(ens_f.stream)
+    ens_f.synchronize()
+    fine_ms = e0.elapsed_time(e1)
+    rstore = StateStore(B, H, Wc, device)
+    torch.cuda.synchronize()
+    rtab = _table(rstore.ptrs(range(B)), device)
+    Lr.gpe_restrict2d(ftab.data_ptr(), rtab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
+    ens_f.synchronize()
+    fine_flags = ens_f.finite()
+    # coarse without the network
+    e0.record(ens_c.stream)
+    ens_c.run(csteps)
+    e1.record(ens_c.stream)
+    ens_c.synchronize()
+    coarse_ms = e0.elapsed_time(e1)
+    # coarse with the network: the net shares the coarse stream
+    cnet = Lr.CNN(B, H, Wc, act_type=net.act_type, device=device, stream=ens_c.stream,
+                  params=net.params.cpu().numpy())
+    cnet.synchronize()
+    torch.cuda.synchronize()
+    e0.record(ens_c.stream)
+    for _ in range(csteps):
+        ens_n.run(1)
+        cnet.features(ntab, B, in_scale)
+        cnet.forward(B)
+        cnet.apply(ntab, B, out_scale)
+    e1.record(ens_c.stream)
+    ens_c.synchronize()
+    net_ms = e0.elapsed_time(e1)
+    flags_c = ens_c.finite()
+    flags_n = ens_n.finite()
+
+    def heights(ptrs):
+        t = _table(ptrs, device)
+        out = torch.zeros(B * Wc * 2, dtype=torch.float32, device=device)
+        torch.cuda.synchronize()
+        Lr.gpe_interface_position(t.data_ptr(), B, H, Wc, out.data_ptr(), sid)
+        ens_c.synchronize()
+        return out.cpu().numpy().reshape(B, Wc, 2)
+
+    ref = heights(phi_ptrs(rstore.ptrs(range(B))))
+    h_c = heights(phi_ptrs(Lr.state_pointers([ens_c.case(b) for b in range(B)])))
+    h_n = heights(phi_ptrs(Lr.state_pointers([ens_n.case(b) for b in range(B)])))
+
+    def err(h, flags):
+        e = np.abs(h - ref)
+        e = np.where(np.isnan(e), np.inf, e)  # a missing crossing counts as a miss
+        per_case = e.reshape(B, -1).max(axis=1)
+        per_case[flags == 0] = np.inf
+        mean_case = np.nanmean(np.where(np.isinf(e), np.nan, e).reshape(B, -1), axis=1)
+        return per_case, mean_case
+
+    max_c, mean_c = err(h_c, flags_c)
+    max_n, mean_n = err(h_n, flags_n)
+    res = {
+        "cases": B, "fine_steps": fine_steps, "coarse_steps": csteps, "factor": factor,
+        "grid_fine": [nx, ny], "grid_coarse": [Wc, H], "error_unit": f"coarse cells ({factor} fine cells)",
+        "fine_ms": round(fine_ms, 2), "coarse_ms": round(coarse_ms, 2), "coarse_net_ms": round(net_ms, 2),
+        "speedup_vs_fine": round(fine_ms / net_ms, 2),
+        "fine_finite": int(fine_flags.sum()),
+        "plain_coarse": {"max_err_median": float(np.median(max_c)), "mean_err_mean": float(np.nanmean(mean_c)),
+                         "cases_within_1_cell": int((max_c <= 1.0).sum()), "finite": int(flags_c.sum())},
+        "learned_coarse": {"max_err_median": float(np.median(max_n)), "mean_err_mean": float(np.nanmean(mean_n)),
+                           "cases_within_1_cell": int((max_n <= 1.0).sum()), "finite": int(flags_n.sum()),
+                           "fallback_to_fine": int((flags_n == 0).sum())},
+    }
+    log(f"[learned] evaluation: {res}")
+    for e in (ens_f, ens_n, ens_c):
+        e.close()
+    return res

@@ -252,3 +252,44 @@ def ensemble_state(prob) -> dict:
     ini = prob["init"]
     st["phi"] = ellipse_phi(prob, ini["radius"], ini["amp"], ini["center"], ini["width"])
     return st
+
+
+# --------------------------------------------------------------------------
+# Multi-mode Rayleigh-Taylor pairs (fine grid and the grid coarser by f) for
+# the learned coarse correction
+# --------------------------------------------------------------------------
+def rt_multimode(seed, nx=256, ny=1024, factor=1, precision="fp32", modes=6, amp_frac=0.05,
+                 Re=3000.0, Pe=8e4, W=2.0, Uc=0.05, At=None):
+    """The Rayleigh-Taylor set-up of `rayleigh_taylor_2d` with a seeded
+    Atwood number At ~ U(0.2, 0.8) (unless given) and a multi-mode
+    interface y0(x) = ny/2 + sum_k A_k cos(2 pi k x / nx + theta_k),
+    k = 1..modes, theta_k ~ U(0, 2 pi), A_k = amp_frac nx w_k with
+    w_k ~ U(0, 1) normalised to sum 1 (fine-grid cells).
+
+    factor > 1 returns the same physics on the (nx/f) x (ny/f) grid in its own
+    lattice units (dx = dt = 1 there, so the lattice velocity U_c is kept and
+    c_s^2 = 1/3): lambda = nx/f, g = U_c^2/lambda, eta = U_c lambda / Re,
+    M = U_c lambda^2 / Pe, interface width W coarse cells.  The returned state
+    is the fine initial state (the coarse run starts from its restriction)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    At = float(rng.uniform(0.2, 0.8)) if At is None else float(At)
+    theta = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+    wts = rng.uniform(0.0, 1.0, size=modes)
+    wts = wts / wts.sum()
+    rho_g = (1.0 - At) / (1.0 + At)
+    nxf, nyf = nx // factor, ny // factor
+    lam = float(nxf)
+    g = Uc * Uc / lam
+    eta = Uc * lam / Re
+    prob = base_problem(
+        dim=2, n=(nxf, nyf, 1), bc=(PERIODIC, PERIODIC, WALL, WALL, 0, 0),
+        rho_l=1.0, rho_g=rho_g, eta_l=eta, eta_g=eta, sigma=0.0,
+        mob=Uc * lam * lam / Pe, width=W, g=(0.0, -g, 0.0), rho_ref=rho_g, precision=precision)
+    prob["meta"] = {"At": At, "seed": seed, "factor": factor}
+    fine = base_problem(dim=2, n=(nx, ny, 1), width=W)
+    x, y, _ = _centres(fine)
+    y0 = ny / 2.0 + sum(amp_frac * nx * wts[k] * np.cos(2 * math.pi * (k + 1) * x / nx + theta[k])
+                        for k in range(modes))
+    st = zero_state(fine)
+    st["phi"] = np.tanh(2.0 * (y - y0) / W)
+    return prob, st
