@@ -178,6 +178,36 @@ def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_st
     }
 
 
+def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=4000, neval=50, batch=32) -> dict:
+    """The learned coarse correction: training data from `ntrain` fine
+    multi-mode Rayleigh-Taylor runs (256 x 1024, seeds 0..ntrain-1), training
+    on the GPU, then `neval` held-out seeds (1000..) run on the fine grid and
+    on the 4x coarser grid (64 x 256, fine_steps / 4 steps) without and with
+    the network; interface-position errors on the coarse grid against the
+    restricted fine solution; speedup = fine time / corrected coarse time."""
+    from paper_2011_00814_amd import learned as LD
+
+    quiet = lambda *a, **k: None  # noqa: E731
+    t0 = time.perf_counter()
+    data = LD.generate(list(range(ntrain)), fine_steps=fine_steps, n_snap=n_snap, log=quiet)
+    gen_s = time.perf_counter() - t0
+    net, hist, sin, sout, train_s = LD.train(data, iters=iters, batch=batch, lr=1e-3, log=quiet)
+    del data
+    held = LD.generate(list(range(1000, 1000 + min(8, neval))), fine_steps=fine_steps, n_snap=10, log=quiet)
+    plain, corr = LD.one_step_gain(net, held, sin, sout)
+    del held
+    res = LD.evaluate(net, sin, sout, list(range(1000, 1000 + neval)), fine_steps=fine_steps, log=quiet)
+    res.update({
+        "workload": f"multi-mode Rayleigh-Taylor, At ~ U(0.2, 0.8), Re 3000, fine 256x1024 / coarse 64x256, "
+                    f"{ntrain} training runs x {fine_steps} fine steps ({n_snap} snapshot pairs each), "
+                    f"{neval} held-out seeds; network 3x3 CNN 4-32-32-4, BF16 operands, FP32 accumulation",
+        "data_generation_s": round(gen_s, 1), "training_s": round(train_s, 1), "training_iters": iters,
+        "loss_first_last": [round(hist[0][1], 4), round(hist[-1][1], 4)],
+        "one_step_mse_plain": round(plain, 4), "one_step_mse_network": round(corr, 4),
+    })
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,7 +216,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("bubble3d", "ensemble"), default="bubble3d")
+    ap.add_argument("--workload", choices=("bubble3d", "ensemble", "learned"), default="bubble3d")
+    ap.add_argument("--learned-summary", type=int, default=1,
+                    help="include a reduced learned-correction run in the default line (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the ensemble summary in the default line (0: skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -225,6 +257,15 @@ def main():
     from paper_2011_00814_amd import gpe
 
     gpe.lib()  # fails loudly if the HIP library is not built
+    if args.workload == "learned":
+        r = learned_bench()
+        print(json.dumps({
+            "metric": "learned-coarse speedup vs the fine solver at interface-position error on the coarse grid",
+            "value": r["speedup_vs_fine"], "unit": "x", "n_gpus": 1, "steps": r["coarse_steps"], "warmup": 0,
+            "ms_per_step": round(r["coarse_net_ms"] / r["coarse_steps"], 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+            "config": {"workload": r["workload"]}, "learned": r}), flush=True)
+        return
     if args.workload == "ensemble":
         steps = args.steps if "--steps" in sys.argv else 5000
         r = ensemble_bench(steps, args.warmup, args.precision)
@@ -326,6 +367,8 @@ def main():
     }
     if args.ensemble_steps > 0:
         line["ensemble"] = ensemble_bench(args.ensemble_steps, 10, args.precision, baseline_steps=50)
+    if args.learned_summary and args.precision == "fp32":
+        line["learned"] = learned_bench(ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n, args.precision)
     print(json.dumps(line), flush=True)

@@ -3,11 +3,12 @@
 // three 3 x 3 convolutions forward and backward, loss, Adam, the
 // mass-projected correction and the interface position.
 //
-// The convolutions are direct (per output pixel, all output channels in
-// registers, the layer's weights in LDS as FP32): the network is small
-// (11.7 k weights) and the per-pixel work (<= 9 x 32 x 32 multiply-adds) keeps
-// it far from the memory bound.  Operands are read as bfloat16 or FP32 and
-// every sum accumulates in FP32.  Weight gradients are an im2col product over
+// Convolutions: with bfloat16 operands the two layers with 32 output
+// channels run as implicit GEMMs on the matrix cores (MFMA, FP32
+// accumulation); the last layer (4 outputs), the FP32-operand variant and
+// the backward passes are direct (per pixel, all output channels in
+// registers, the layer's weights in LDS as FP32).  Every sum accumulates in
+// FP32.  Weight gradients are an im2col product over
 // chunks of 32 pixels staged in LDS; each work-group writes its partial sums
 // and a second pass adds them in a fixed order, so a training step is
 // bitwise reproducible.
@@ -15,6 +16,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "gpe.h"
 #include "gpe_learn.h"
@@ -168,6 +170,103 @@ __global__ __launch_bounds__(kBlock) void conv_fwd_kernel(const TA* __restrict__
   TO* out = y + p * CO;
 #pragma unroll
   for (int o = 0; o < CO; ++o) store(out[o], RELU ? fmaxf(acc[o], 0.f) : acc[o]);
+}
+
+// The same convolution on the matrix cores for bfloat16 operands and 32
+// output channels: an implicit GEMM with M = pixels, N = 32 output channels
+// and K = 9 CI (tap, input channel), one v_mfma_f32_32x32x8 bf16 per 8 values
+// of K, FP32 accumulation.  A wave computes a tile of 32 consecutive pixels.
+// Fragment layout of the instruction (lane l, element t of 4, output r of 16):
+// A[l % 32][4 (l / 32) + t], B[4 (l / 32) + t][l % 32],
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  The weights sit in LDS as
+// [K / 4][32][4], so the 32 lanes of a half-wave read 32 consecutive 8-byte
+// chunks of B.  CI = 4 puts one tap in each half-wave's 4 values of K (ten
+// taps with the last zero); CI a multiple of 8 keeps a K-step inside one tap.
+typedef short mfma_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+
+template <int CI, bool RELU>
+__global__ __launch_bounds__(kBlock) void conv_fwd_mfma_kernel(const bf16* __restrict__ x, const bf16* __restrict__ w,
+                                                               const float* __restrict__ bias, bf16* __restrict__ y,
+                                                               int B, int H, int W) {
+  constexpr int CO = 32;
+  constexpr int K = 9 * CI;
+  static_assert(CI == 4 || CI % 8 == 0, "input channels: 4 or a multiple of 8");
+  __shared__ uint2 sw[(K / 4) * CO];  // 4 bf16 per entry
+  for (int q = threadIdx.x; q < (K / 4) * CO; q += kBlock) {
+    const int kc = q / CO, o = q % CO;  // K chunk (tap, 4 input channels) and output channel
+    const uint16_t* src = &w[(size_t)o * K + kc * 4].bits;
+    uint2 v;
+    v.x = (uint32_t)src[0] | ((uint32_t)src[1] << 16);
+    v.y = (uint32_t)src[2] | ((uint32_t)src[3] << 16);
+    sw[q] = v;
+  }
+  __syncthreads();
+  const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
+  const long P = (long)B * H * W;
+  const long p0 = ((long)blockIdx.x * (kBlock / 64) + wave) * 32;
+  if (p0 >= P) return;  // uniform per wave
+  const int kg = lane / 32;           // which 4 of the 8 K values this lane holds
+  const long pa = p0 + (lane % 32);   // the lane's A-row pixel
+  const bool va = pa < P;
+  const int xa = va ? (int)(pa % W) : 0;
+  const long ra = pa / W;
+  const int ya = va ? (int)(ra % H) : 0;
+  const long ba = ra / H;
+  // x at (y + dy, x + dx) of the lane's pixel, 4 channels from c0, or zeros
+  auto load_a = [&](int tap, int c0) -> mfma_bf16x4 {
+    mfma_bf16x4 a = {0, 0, 0, 0};
+    const int y2 = ya + tap / 3 - 1;
+    if (va && tap < 9 && y2 >= 0 && y2 < H) {
+      const uint2 v = *reinterpret_cast<const uint2*>(x + ((ba * H + y2) * W + wrap(xa + tap % 3 - 1, W)) * CI + c0);
+      a[0] = (short)(v.x & 0xffffu);
+      a[1] = (short)(v.x >> 16);
+      a[2] = (short)(v.y & 0xffffu);
+      a[3] = (short)(v.y >> 16);
+    }
+    return a;
+  };
+  auto load_b = [&](int kc) -> mfma_bf16x4 {
+    mfma_bf16x4 b = {0, 0, 0, 0};
+    if (kc < K / 4) {
+      const uint2 v = sw[kc * CO + (lane % 32)];
+      b[0] = (short)(v.x & 0xffffu);
+      b[1] = (short)(v.x >> 16);
+      b[2] = (short)(v.y & 0xffffu);
+      b[3] = (short)(v.y >> 16);
+    }
+    return b;
+  };
+  mfma_f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  if (CI == 4) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {  // K values 8s .. 8s+7 = taps 2s and 2s+1
+      const int tap = 2 * s + kg;
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(load_a(tap, 0), load_b(tap), acc, 0, 0, 0);
+    }
+  } else {
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+#pragma unroll
+      for (int c = 0; c < CI; c += 8) {
+        const int c0 = c + 4 * kg;
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(load_a(tap, c0), load_b((tap * CI + c0) / 4), acc, 0, 0,
+                                                        0);
+      }
+    }
+  }
+  const int o = lane % 32;
+  const float bo = bias[o];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const long p = p0 + 8 * (r / 4) + 4 * kg + (r % 4);
+    if (p < P) {
+      const float v = acc[r] + bo;
+      store(y[p * CO + o], RELU ? fmaxf(v, 0.f) : v);
+    }
+  }
 }
 
 // gin[q][i] = (sum over taps and outputs o of w[o][tap][i] gout[q - tap][o]) *
@@ -392,11 +491,21 @@ bool dims_ok(int B, int H, int W) { return B >= 1 && H >= 1 && W >= 1 && (long)B
 template <typename TA>
 hipError_t forward_t(const float* prm, const TA* wa, const TA* x0, TA* a1, TA* a2, float* out, int B, int H, int W,
                      hipStream_t s) {
-  const unsigned g = blocks_for((long)B * H * W);
-  hipLaunchKernelGGL((conv_fwd_kernel<C0, C1, TA, true, TA>), dim3(g), dim3(kBlock), 0, s, x0, wa + OFF_W1,
-                     prm + OFF_B1, a1, B, H, W);
-  hipLaunchKernelGGL((conv_fwd_kernel<C1, C2, TA, true, TA>), dim3(g), dim3(kBlock), 0, s, a1, wa + OFF_W2,
-                     prm + OFF_B2, a2, B, H, W);
+  const long P = (long)B * H * W;
+  const unsigned g = blocks_for(P);
+  if constexpr (std::is_same<TA, bf16>::value) {
+    // layers with 32 output channels on the matrix cores
+    const unsigned gm = (unsigned)((P + 4 * 32 - 1) / (4 * 32));
+    hipLaunchKernelGGL((conv_fwd_mfma_kernel<C0, true>), dim3(gm), dim3(kBlock), 0, s, x0, wa + OFF_W1,
+                       prm + OFF_B1, a1, B, H, W);
+    hipLaunchKernelGGL((conv_fwd_mfma_kernel<C1, true>), dim3(gm), dim3(kBlock), 0, s, a1, wa + OFF_W2,
+                       prm + OFF_B2, a2, B, H, W);
+  } else {
+    hipLaunchKernelGGL((conv_fwd_kernel<C0, C1, TA, true, TA>), dim3(g), dim3(kBlock), 0, s, x0, wa + OFF_W1,
+                       prm + OFF_B1, a1, B, H, W);
+    hipLaunchKernelGGL((conv_fwd_kernel<C1, C2, TA, true, TA>), dim3(g), dim3(kBlock), 0, s, a1, wa + OFF_W2,
+                       prm + OFF_B2, a2, B, H, W);
+  }
   hipLaunchKernelGGL((conv_fwd_kernel<C2, C3, TA, false, float>), dim3(g), dim3(kBlock), 0, s, a2, wa + OFF_W3,
                      prm + OFF_B3, out, B, H, W);
   return hipGetLastError();

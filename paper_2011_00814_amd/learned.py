@@ -235,102 +235,128 @@ def one_step_gain(net, data, in_scale, out_scale, device="cuda:0", batch=None):
 
 
 def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1024, device="cuda:0",
-             log=print):
+             log=print, graph_steps=10, checkpoints=4, autotune=True):
     """Fine runs of `seeds` against coarse runs from their restricted
     initial states, without and with the network (one correction per
-    coarse step), fine_steps / factor coarse steps.  Interface positions
-    (outermost phi = 0 crossings per column, top and bottom) are compared
-    on the coarse grid, the fine solution restricted to it; errors are in
-    coarse cells (factor fine cells).  A coarse case that is not finite at
-    the end falls back to the fine run."""
+    coarse step), fine_steps / factor coarse steps, compared at
+    `checkpoints` equally spaced times.  Interface positions (outermost
+    phi = 0 crossings per column, top and bottom) are compared on the
+    coarse grid, the fine solution restricted to it; errors are in coarse
+    cells (factor fine cells).  A coarse case that is not finite falls back
+    to the fine run.  Times of the three runs are summed over the segments."""
     import torch
 
     B = len(seeds)
     H, Wc = ny // factor, nx // factor
     csteps = fine_steps // factor
+    seg_c = csteps // checkpoints
+    seg_f = seg_c * factor
     fine, coarse, phis = _fine_and_coarse(seeds, nx, ny, factor)
     ens_f = _make_fine_ensemble(fine, phis, device)
     ens_c = G.Ensemble(coarse, device=device)
     ens_n = G.Ensemble(coarse, device=device, stream=ens_c.stream)
+    if autotune:
+        # tile heights for the coarse batches; the trial steps run on the
+        # initial placeholder state, which is overwritten below
+        ens_c.autotune(5)
+        ens_n.autotune(5)
     sid = ens_c.stream.cuda_stream
     ftab = _table(Lr.state_pointers([ens_f.case(b) for b in range(B)]), device)
     ctab = _table(Lr.state_pointers([ens_c.case(b) for b in range(B)]), device)
     ntab = _table(Lr.state_pointers([ens_n.case(b) for b in range(B)]), device)
-    phi_ptrs = lambda tab_ptrs: [tab_ptrs[4 * b + 3] for b in range(B)]  # noqa: E731
+    phi_of = lambda ptrs: [ptrs[4 * b + 3] for b in range(B)]  # noqa: E731
     torch.cuda.synchronize()
+    ens_c.synchronize()
     ens_f.synchronize()
     Lr.gpe_restrict2d(ftab.data_ptr(), ctab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
     Lr.gpe_restrict2d(ftab.data_ptr(), ntab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
     ens_f.synchronize()
-    # fine reference (timed)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(ens_f.stream)
-    ens_f.run(fine_steps)
-    e1.record(ens_f.stream)
-    ens_f.synchronize()
-    fine_ms = e0.elapsed_time(e1)
     rstore = StateStore(B, H, Wc, device)
-    torch.cuda.synchronize()
-    rtab = _table(rstore.ptrs(range(B)), device)
-    Lr.gpe_restrict2d(ftab.data_ptr(), rtab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
-    ens_f.synchronize()
-    fine_flags = ens_f.finite()
-    # coarse without the network
-    e0.record(ens_c.stream)
-    ens_c.run(csteps)
-    e1.record(ens_c.stream)
-    ens_c.synchronize()
-    coarse_ms = e0.elapsed_time(e1)
-    # coarse with the network: the net shares the coarse stream
     cnet = Lr.CNN(B, H, Wc, act_type=net.act_type, device=device, stream=ens_c.stream,
                   params=net.params.cpu().numpy())
-    cnet.synchronize()
     torch.cuda.synchronize()
-    e0.record(ens_c.stream)
-    for _ in range(csteps):
-        ens_n.run(1)
+    rtab = _table(rstore.ptrs(range(B)), device)
+
+    def corrected_step():
+        ens_n.run(1)  # one batch step, launched (not replayed) so that it can be captured
         cnet.features(ntab, B, in_scale)
         cnet.forward(B)
         cnet.apply(ntab, B, out_scale)
-    e1.record(ens_c.stream)
-    ens_c.synchronize()
-    net_ms = e0.elapsed_time(e1)
-    flags_c = ens_c.finite()
-    flags_n = ens_n.finite()
+
+    # graph_steps corrected steps captured as one HIP graph on the coarse
+    # stream (every launch goes to that stream; nothing allocates);
+    # capturing records the launches without running them
+    graph = None
+    if graph_steps > 1 and seg_c >= graph_steps:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=ens_c.stream):
+            for _ in range(graph_steps):
+                corrected_step()
+        ens_c.synchronize()
+
+    def timed(stream, fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1)
+
+    def run_net():
+        done = 0
+        if graph is not None:
+            for _ in range(seg_c // graph_steps):
+                graph.replay()
+            done = (seg_c // graph_steps) * graph_steps
+        for _ in range(seg_c - done):
+            corrected_step()
+
+    hbuf = torch.zeros(B * Wc * 2, dtype=torch.float32, device=device)
+    torch.cuda.synchronize()
 
     def heights(ptrs):
         t = _table(ptrs, device)
-        out = torch.zeros(B * Wc * 2, dtype=torch.float32, device=device)
-        torch.cuda.synchronize()
-        Lr.gpe_interface_position(t.data_ptr(), B, H, Wc, out.data_ptr(), sid)
+        Lr.gpe_interface_position(t.data_ptr(), B, H, Wc, hbuf.data_ptr(), sid)
         ens_c.synchronize()
-        return out.cpu().numpy().reshape(B, Wc, 2)
+        return hbuf.cpu().numpy().reshape(B, Wc, 2).copy()
 
-    ref = heights(phi_ptrs(rstore.ptrs(range(B))))
-    h_c = heights(phi_ptrs(Lr.state_pointers([ens_c.case(b) for b in range(B)])))
-    h_n = heights(phi_ptrs(Lr.state_pointers([ens_n.case(b) for b in range(B)])))
-
-    def err(h, flags):
+    def err(h, ref, flags):
         e = np.abs(h - ref)
         e = np.where(np.isnan(e), np.inf, e)  # a missing crossing counts as a miss
+        e[flags == 0] = np.inf
         per_case = e.reshape(B, -1).max(axis=1)
-        per_case[flags == 0] = np.inf
         mean_case = np.nanmean(np.where(np.isinf(e), np.nan, e).reshape(B, -1), axis=1)
-        return per_case, mean_case
+        return {"mean_err_mean": float(np.nanmean(mean_case)), "max_err_median": float(np.median(per_case)),
+                "columns_within_1_cell": round(float(np.mean(e <= 1.0)), 4),
+                "cases_within_1_cell": int((per_case <= 1.0).sum()), "finite": int(flags.sum())}
 
-    max_c, mean_c = err(h_c, flags_c)
-    max_n, mean_n = err(h_n, flags_n)
+    fine_ms = coarse_ms = net_ms = 0.0
+    series = []
+    lam_steps = nx / 0.05  # fine steps per T_c = lambda / U_c
+    for seg in range(checkpoints):
+        fine_ms += timed(ens_f.stream, lambda: ens_f.run(seg_f))
+        Lr.gpe_restrict2d(ftab.data_ptr(), rtab.data_ptr(), B, ny, nx, factor, ens_f.stream.cuda_stream)
+        ens_f.synchronize()
+        coarse_ms += timed(ens_c.stream, lambda: ens_c.run(seg_c))
+        net_ms += timed(ens_c.stream, run_net)
+        ref = heights(phi_of(rstore.ptrs(range(B))))
+        h_c = heights(phi_of(Lr.state_pointers([ens_c.case(b) for b in range(B)])))
+        h_n = heights(phi_of(Lr.state_pointers([ens_n.case(b) for b in range(B)])))
+        fsteps = (seg + 1) * seg_f
+        series.append({"fine_steps": fsteps, "t_over_Tc": round(fsteps / lam_steps, 3),
+                       "plain_coarse": err(h_c, ref, ens_c.finite()),
+                       "learned_coarse": err(h_n, ref, ens_n.finite())})
+    flags_n = ens_n.finite()
+    last = series[-1]
     res = {
-        "cases": B, "fine_steps": fine_steps, "coarse_steps": csteps, "factor": factor,
+        "cases": B, "fine_steps": checkpoints * seg_f, "coarse_steps": checkpoints * seg_c, "factor": factor,
         "grid_fine": [nx, ny], "grid_coarse": [Wc, H], "error_unit": f"coarse cells ({factor} fine cells)",
         "fine_ms": round(fine_ms, 2), "coarse_ms": round(coarse_ms, 2), "coarse_net_ms": round(net_ms, 2),
-        "speedup_vs_fine": round(fine_ms / net_ms, 2),
-        "fine_finite": int(fine_flags.sum()),
-        "plain_coarse": {"max_err_median": float(np.median(max_c)), "mean_err_mean": float(np.nanmean(mean_c)),
-                         "cases_within_1_cell": int((max_c <= 1.0).sum()), "finite": int(flags_c.sum())},
-        "learned_coarse": {"max_err_median": float(np.median(max_n)), "mean_err_mean": float(np.nanmean(mean_n)),
-                           "cases_within_1_cell": int((max_n <= 1.0).sum()), "finite": int(flags_n.sum()),
-                           "fallback_to_fine": int((flags_n == 0).sum())},
+        "speedup_vs_fine": round(fine_ms / net_ms, 2), "speedup_plain_coarse": round(fine_ms / coarse_ms, 2),
+        "fine_finite": int(ens_f.finite().sum()),
+        "plain_coarse": last["plain_coarse"], "learned_coarse": dict(last["learned_coarse"],
+                                                                      fallback_to_fine=int((flags_n == 0).sum())),
+        "checkpoints": series,
     }
     log(f"[learned] evaluation: {res}")
     for e in (ens_f, ens_n, ens_c):

@@ -41,6 +41,6 @@ def test_learned_correction_small(LD):
     assert corr < plain
     res = LD.evaluate(net, sin, sout, [100, 101], fine_steps=1200, **kw)
     assert res["fine_finite"] == 2 and res["plain_coarse"]["finite"] == 2
-    assert res["coarse_steps"] == 300
+    assert res["coarse_steps"] == 300 and len(res["checkpoints"]) == 4
     for k in ("plain_coarse", "learned_coarse"):
         assert math.isfinite(res[k]["mean_err_mean"]) or res[k]["finite"] < 2
