@@ -69,6 +69,19 @@ enum gpe_init_kind {
                             a = R (1 + init_amp), b = R (1 - init_amp), |init_amp| < 1 */
 };
 
+/* Convection term of the Cahn-Hilliard equation (Sec. 2), with the frozen
+ * space-time averaged centre velocity u_hat and the isotropic first
+ * derivative (Sec. 3):
+ *  - GPE_CH_CONSERVATIVE: div(phi u_hat), the isotropic divergence of the
+ *    product.  The phase mass sum(phi) is conserved to round-off.  It
+ *    differs from the advective form by phi div(u_hat), which couples phi to
+ *    the acoustic divergence in the bulk phases; with a light gas phase
+ *    (density ratio ~50) that coupling grows at the grid scale.
+ *  - GPE_CH_ADVECTIVE: u_hat . grad(phi), the equation as printed; the
+ *    phase mass then drifts by O(sum phi div u_hat).
+ * The batched ensemble (gpe_ensemble_*) supports the conservative form only. */
+enum gpe_ch_transport { GPE_CH_CONSERVATIVE = 0, GPE_CH_ADVECTIVE = 1 };
+
 /* Physical and numerical parameters in lattice units (dx = 1). */
 typedef struct gpe_params {
   int32_t geometry;        /* gpe_geometry                                             */
@@ -80,7 +93,7 @@ typedef struct gpe_params {
                               periodic on both sides or on neither                      */
   int32_t lattice;         /* GPE_D2Q9 in 2-D/axisym; GPE_D3Q15/19/27 in 3-D           */
   int32_t allow_unstable;  /* 1: skip the GPE_EUNSTABLE check of gpe_init_state        */
-  int32_t reserved0;       /* must be 0                                                */
+  int32_t ch_transport;    /* gpe_ch_transport: form of the CH convection term          */
   double dt;               /* time step                                                */
   double cs2;              /* c_s^2 of the pressure equation                          */
   double rho_l, rho_g;     /* densities of liquid (phi = +1) and gas (phi = -1)       */
@@ -107,7 +120,7 @@ typedef struct gpe_problem {
   int32_t bc[6];
   int32_t lattice;
   int32_t capillary_scale; /* 1: U_c = sigma / eta_L (flows with surface tension)     */
-  int32_t reserved0;       /* must be 0                                                */
+  int32_t ch_transport;    /* gpe_ch_transport, copied to gpe_params                    */
   double N_L;              /* cells per characteristic length L_c                     */
   double N_t;              /* steps per characteristic time T_c                       */
   double r_rho;            /* rho_L / rho_G (rho_L = 1)                                */

@@ -101,6 +101,8 @@ def _params(prob: dict) -> _Params:
         P.bc[s] = int(prob["bc"][s])
     P.lattice = int(prob["lattice"])
     P.flags = int(prob.get("flags", 0))
+    if int(prob.get("ch_transport", 0)) == 1:  # the CH equation's advective form as printed
+        P.flags |= ADVECTIVE_CH
     P.ch_rk = int(prob.get("ch_rk", 0))
     for key in ("dt", "cs2", "rho_l", "rho_g", "eta_l", "eta_g", "sigma", "mob", "width", "rho_ref"):
         setattr(P, key, float(prob[key]))

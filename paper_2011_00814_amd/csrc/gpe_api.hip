@@ -74,6 +74,7 @@ int validate(const gpe_params* p) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->g[a])) return GPE_EINVAL;
   if (!std::isfinite(p->rho_ref)) return GPE_EINVAL;
+  if (p->ch_transport != GPE_CH_CONSERVATIVE && p->ch_transport != GPE_CH_ADVECTIVE) return GPE_EINVAL;
   if (p->init_kind < 0 || p->init_kind > 4) return GPE_EINVAL;
   if (p->init_kind == GPE_INIT_ELLIPSE && (!(p->init_radius > 0) || !(std::fabs(p->init_amp) < 1.0)))
     return GPE_EINVAL;
@@ -343,6 +344,7 @@ int ch_args(const gpe_state* s, int zchunk, ChArgs<T> a[4], int stage[4]) {
   h.g = s->grid;
   h.g.zchunk = zchunk;
   h.c = make_consts<T>(&s->P, s->dim);
+  h.adv = s->P.ch_transport == GPE_CH_ADVECTIVE ? 1 : 0;
   for (int q = 0; q < 3; ++q) h.usum[q] = buf<T>(s, B_US + q);
   T* phi = buf<T>(s, B_PHI);
   T* pa = buf<T>(s, B_PHA);
@@ -383,6 +385,7 @@ int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out) {
   for (int a = 0; a < 3; ++a) out->n[a] = in->n[a];
   for (int a = 0; a < 6; ++a) out->bc[a] = in->bc[a];
   out->lattice = in->lattice;
+  out->ch_transport = in->ch_transport;
   // dx = L_c / N_L = 1, dt = T_c / N_t = 1, U_c = L_c / T_c = N_L / N_t
   const double Uc = in->N_L / in->N_t;
   out->dt = 1.0;

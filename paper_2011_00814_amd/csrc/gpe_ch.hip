@@ -2,16 +2,22 @@
 // Sec. 2 CH equation and chemical potential, Sec. 3 isotropic lattice
 // stencils, TVD-RK2 / RK4 integration, space-time averaged centre velocity).
 //
-// Right-hand side (conservative transport of phi by the frozen centre
-// velocity u_hat, mobility M, chemical potential mu(phi)):
+// Right-hand side (transport of phi by the frozen centre velocity u_hat,
+// mobility M, chemical potential mu(phi)), conservative form (ADV = false):
 //   L = -3 sum_i w_i e_i . (phi u_hat)(x + e_i) + 6 M sum_i w_i (mu(x + e_i) - mu(x))
-// In axisymmetric geometry the flux is the isotropic divergence of r phi u_hat
-// divided by r, and every Laplacian link is weighted by its mid-point radius.
+// or advective form (ADV = true, the CH equation as printed):
+//   L = -3 u_hat(x) . sum_i w_i e_i phi(x + e_i) + 6 M sum_i w_i (mu(x + e_i) - mu(x))
+// In axisymmetric geometry the conservative flux is the isotropic divergence
+// of r phi u_hat divided by r (the advective gradient carries no radius), and
+// every Laplacian link is weighted by its mid-point radius.
 //
 // A work-group owns TX x TY columns and marches along Z.  For each new plane
 // m = k+1 it stages phi (plane m+1) and the face velocity sums, then forms
 // mu(m) and the flux vector F(m) = phi u_hat once in LDS rings; the output
-// plane k reads mu and F from planes k-1, k, k+1.
+// plane k reads mu and F from planes k-1, k, k+1.  In the advective form the
+// F_X ring holds a copy of phi(m) instead (the phi ring has already dropped
+// plane k-1 when plane k is written) and each thread keeps the centre
+// velocity of its own cell in registers from derive(k) to output(k).
 #include <type_traits>
 
 #include "gpe_plane.hpp"
@@ -24,7 +30,7 @@ template <typename T>
 struct ChOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 2; };
 
 // One work-group tile (btx, bty) x Z chunk btz of the grid described by A.
-template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY, bool ADV>
 __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int bty, int btz) {
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 4;                  // in-plane X range [-2, TX+1]
@@ -148,6 +154,10 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
         }
       }
       b[(S_MU + SC) * PLANE] = c.a4 * f * (f * f - T(1)) - c.kappa6 * lap;
+      if (ADV) {
+        b[(S_FX + SC) * PLANE] = f;
+        continue;
+      }
       // centre velocity = 1/4 of the sums over its two faces; the factor 1/4
       // is applied in the flux divergence
       const T pr = AXI ? f * rnode : f;
@@ -164,6 +174,9 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   constexpr bool NEED_PHIS = STAGE == CH_RK2_2 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3;
   constexpr bool NEED_ACC = STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
   T phis_cur = T(0), acc_cur = T(0), phis_next = T(0), acc_next = T(0);
+  // advective form: 4 u_hat of the own cell (sums over its two faces) of the
+  // plane being written and of the next one
+  T uc_cur[3] = {T(0), T(0), T(0)}, uc_next[3] = {T(0), T(0), T(0)};
   auto fetch_pt = [&](int k, T& ps, T& ac) {
     if (active && k >= z0 && k < z1) {
       const size_t po = (size_t)k * ny * nx;
@@ -174,7 +187,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
 
   // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP);
   // phc = phi(k) at the own cell
-  auto output = [&](int k, auto s0, T phc, T ps, T ac) {
+  auto output = [&](int k, auto s0, T phc, T ps, T ac, T ucx, T ucy, T ucz) {
     constexpr int S0 = decltype(s0)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     const T* M0 = L0 + (S_MU + S0) * PLANE;
@@ -202,40 +215,80 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
       const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + (rp * (Mp[0] - mc) + rm * (Mm[0] - mc));
       const T s2 = rp * ((Mp[1] - mc) + (Mp[-1] - mc)) + rm * ((Mm[1] - mc) + (Mm[-1] - mc));
       lap = c.w1 * s1 + c.w2 * s2;
-      // D2Q9 in the (X, Z) plane: axis links and the four diagonals
-      const T f1 = (X0[1] - X0[-1]) + (Zp[0] - Zm[0]);
-      const T f2 = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
-      flux = (c.w1 * f1 + c.w2 * f2) * inv_r;
+      if (!ADV) {
+        // D2Q9 in the (X, Z) plane: axis links and the four diagonals
+        const T f1 = (X0[1] - X0[-1]) + (Zp[0] - Zm[0]);
+        const T f2 = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
+        flux = (c.w1 * f1 + c.w2 * f2) * inv_r;
+      } else {
+        // isotropic gradient of phi (held in the F_X ring) along X and Z
+        const T gx = c.w1 * (X0[1] - X0[-1]) + c.w2 * ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1]));
+        const T gz = c.w1 * (Xp[0] - Xm[0]) + c.w2 * ((Xp[1] + Xp[-1]) - (Xm[1] + Xm[-1]));
+        flux = ucx * gx + ucz * gz;
+      }
     } else {
       const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + ((M0[EY] - mc) + (M0[-EY] - mc)) +
                    ((Mp[0] - mc) + (Mm[0] - mc));
       lap = c.w1 * s1;
-      flux = c.w1 * ((X0[1] - X0[-1]) + (Y0[EY] - Y0[-EY]) + (Zp[0] - Zm[0]));
+      // advective form: isotropic gradient of phi, held in the F_X ring
+      T gx = T(0), gy = T(0), gz = T(0);
+      if (!ADV) {
+        flux = c.w1 * ((X0[1] - X0[-1]) + (Y0[EY] - Y0[-EY]) + (Zp[0] - Zm[0]));
+      } else {
+        gx = c.w1 * (X0[1] - X0[-1]);
+        gy = c.w1 * (X0[EY] - X0[-EY]);
+        gz = c.w1 * (Xp[0] - Xm[0]);
+      }
       if (c.w2 != T(0)) {
         const T s2 = ((M0[1 + EY] - mc) + (M0[1 - EY] - mc) + (M0[-1 + EY] - mc) + (M0[-1 - EY] - mc)) +
                      ((Mp[1] - mc) + (Mp[-1] - mc) + (Mp[EY] - mc) + (Mp[-EY] - mc)) +
                      ((Mm[1] - mc) + (Mm[-1] - mc) + (Mm[EY] - mc) + (Mm[-EY] - mc));
         lap += c.w2 * s2;
-        // edges: XY in plane k, XZ and YZ in planes k +- 1
-        const T exy = ((X0[1 + EY] + X0[1 - EY]) - (X0[-1 + EY] + X0[-1 - EY])) +
-                      ((Y0[1 + EY] + Y0[-1 + EY]) - (Y0[1 - EY] + Y0[-1 - EY]));
-        const T exz = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
-        const T eyz = ((Yp[EY] - Yp[-EY]) + (Ym[EY] - Ym[-EY])) + ((Zp[EY] + Zp[-EY]) - (Zm[EY] + Zm[-EY]));
-        flux += c.w2 * (exy + (exz + eyz));
+        if (!ADV) {
+          // edges: XY in plane k, XZ and YZ in planes k +- 1
+          const T exy = ((X0[1 + EY] + X0[1 - EY]) - (X0[-1 + EY] + X0[-1 - EY])) +
+                        ((Y0[1 + EY] + Y0[-1 + EY]) - (Y0[1 - EY] + Y0[-1 - EY]));
+          const T exz = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
+          const T eyz = ((Yp[EY] - Yp[-EY]) + (Ym[EY] - Ym[-EY])) + ((Zp[EY] + Zp[-EY]) - (Zm[EY] + Zm[-EY]));
+          flux += c.w2 * (exy + (exz + eyz));
+        } else {
+          // edge links: XY in plane k, XZ / YZ in planes k +- 1
+          const T* P0 = X0;
+          const T* Pp = Xp;
+          const T* Pm = Xm;
+          gx += c.w2 * (((P0[1 + EY] + P0[1 - EY]) - (P0[-1 + EY] + P0[-1 - EY])) +
+                        ((Pp[1] - Pp[-1]) + (Pm[1] - Pm[-1])));
+          gy += c.w2 * (((P0[1 + EY] + P0[-1 + EY]) - (P0[1 - EY] + P0[-1 - EY])) +
+                        ((Pp[EY] - Pp[-EY]) + (Pm[EY] - Pm[-EY])));
+          gz += c.w2 * (((Pp[1] + Pp[-1]) + (Pp[EY] + Pp[-EY])) - ((Pm[1] + Pm[-1]) + (Pm[EY] + Pm[-EY])));
+        }
       }
       if (c.w3 != T(0)) {
         const T s3 = ((Mp[1 + EY] - mc) + (Mp[1 - EY] - mc) + (Mp[-1 + EY] - mc) + (Mp[-1 - EY] - mc)) +
                      ((Mm[1 + EY] - mc) + (Mm[1 - EY] - mc) + (Mm[-1 + EY] - mc) + (Mm[-1 - EY] - mc));
         lap += c.w3 * s3;
-        // corners (sx, sy, sz): sx F_X + sy F_Y + sz F_Z at planes k +- 1
-        auto corner = [&](const T* X, const T* Y) {
-          return ((X[1 + EY] + X[1 - EY]) - (X[-1 + EY] + X[-1 - EY])) +
-                 ((Y[1 + EY] + Y[-1 + EY]) - (Y[1 - EY] + Y[-1 - EY]));
-        };
-        const T zs = ((Zp[1 + EY] + Zp[1 - EY]) + (Zp[-1 + EY] + Zp[-1 - EY])) -
-                     ((Zm[1 + EY] + Zm[1 - EY]) + (Zm[-1 + EY] + Zm[-1 - EY]));
-        flux += c.w3 * ((corner(Xp, Yp) + corner(Xm, Ym)) + zs);
+        if (!ADV) {
+          // corners (sx, sy, sz): sx F_X + sy F_Y + sz F_Z at planes k +- 1
+          auto corner = [&](const T* X, const T* Y) {
+            return ((X[1 + EY] + X[1 - EY]) - (X[-1 + EY] + X[-1 - EY])) +
+                   ((Y[1 + EY] + Y[-1 + EY]) - (Y[1 - EY] + Y[-1 - EY]));
+          };
+          const T zs = ((Zp[1 + EY] + Zp[1 - EY]) + (Zp[-1 + EY] + Zp[-1 - EY])) -
+                       ((Zm[1 + EY] + Zm[1 - EY]) + (Zm[-1 + EY] + Zm[-1 - EY]));
+          flux += c.w3 * ((corner(Xp, Yp) + corner(Xm, Ym)) + zs);
+        } else {
+          // corner links (+-1, +-1, +-1) of phi in planes k +- 1
+          const T* Pp = Xp;
+          const T* Pm = Xm;
+          auto cx = [&](const T* P) { return (P[1 + EY] + P[1 - EY]) - (P[-1 + EY] + P[-1 - EY]); };
+          auto cy = [&](const T* P) { return (P[1 + EY] + P[-1 + EY]) - (P[1 - EY] + P[-1 - EY]); };
+          auto cs = [&](const T* P) { return (P[1 + EY] + P[1 - EY]) + (P[-1 + EY] + P[-1 - EY]); };
+          gx += c.w3 * (cx(Pp) + cx(Pm));
+          gy += c.w3 * (cy(Pp) + cy(Pm));
+          gz += c.w3 * (cs(Pp) - cs(Pm));
+        }
       }
+      if (ADV) flux = (ucx * gx + ucy * gy) + ucz * gz;
     }
     // L = -3 sum_i w_i e_i . F(x + e_i) + 6 M sum_i w_i (mu_i - mu); the
     // stored fluxes carry 4x the centre velocity
@@ -283,10 +336,21 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     __syncthreads();
     derive(k + 1, std::integral_constant<int, S1>{});
     const T phc = L0[(S_PH + SK) * PLANE];
+    if (ADV) {
+      // face sums of plane k+1 (X / Y single slots, Z ring slots of k+1, k+2)
+      uc_next[0] = L0[S_SX * PLANE] + L0[S_SX * PLANE + 1];
+      uc_next[1] = (DIM == 3) ? L0[S_SY * PLANE] + L0[S_SY * PLANE + EY] : T(0);
+      uc_next[2] = L0[(S_SZ + S1) * PLANE] + L0[(S_SZ + S2) * PLANE];
+    }
     __syncthreads();
-    if (k >= z0 && active) output(k, sk, phc, phis_cur, acc_cur);
+    if (k >= z0 && active) output(k, sk, phc, phis_cur, acc_cur, uc_cur[0], uc_cur[1], uc_cur[2]);
     phis_cur = phis_next;
     acc_cur = acc_next;
+    if (ADV) {
+      uc_cur[0] = uc_next[0];
+      uc_cur[1] = uc_next[1];
+      uc_cur[2] = uc_next[2];
+    }
   };
 
   // -------- warm-up: phi(z0-2), phi(z0-1) and the Z sums of plane z0-1 ----
@@ -304,11 +368,11 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
 }
 
 // Single grid: work-group b runs the tile tile_of_block assigns to it.
-template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY, bool ADV>
 __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_kernel(ChArgs<T> A) {
   int btx, bty, btz;
   tile_of_block(A.g, btx, bty, btz);
-  ch_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, btx, bty, btz);
+  ch_stage_tile<T, DIM, AXI, STAGE, TX, TY, ADV>(A, btx, bty, btz);
 }
 
 // Batch of grids: work-group b runs tile tiles[b] = (case, btx, bty, btz)
@@ -318,7 +382,7 @@ __global__ __launch_bounds__(TX* TY, ChOcc<T>::W) void ch_stage_batch_kernel(con
                                                                          const int4* __restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
   const ChArgs<T> A = cases[t.x];
-  ch_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, t.y, t.z, t.w);
+  ch_stage_tile<T, DIM, AXI, STAGE, TX, TY, false>(A, t.y, t.z, t.w);
 }
 
 template <typename T, int DIM, bool AXI, int STAGE>
@@ -329,7 +393,10 @@ static hipError_t launch_ch_t(const ChArgs<T>& a, hipStream_t s) {
   b.g.nb[1] = (a.g.n[1] + TY - 1) / TY;
   b.g.nb[2] = (a.g.n[2] + a.g.zchunk - 1) / a.g.zchunk;
   const unsigned nblk = (unsigned)(b.g.nb[0] * b.g.nb[1] * b.g.nb[2]);
-  hipLaunchKernelGGL((ch_stage_kernel<T, DIM, AXI, STAGE, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, b);
+  if (a.adv)
+    hipLaunchKernelGGL((ch_stage_kernel<T, DIM, AXI, STAGE, TX, TY, true>), dim3(nblk), dim3(TX * TY), 0, s, b);
+  else
+    hipLaunchKernelGGL((ch_stage_kernel<T, DIM, AXI, STAGE, TX, TY, false>), dim3(nblk), dim3(TX * TY), 0, s, b);
   return hipGetLastError();
 }
 

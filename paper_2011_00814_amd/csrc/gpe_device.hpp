@@ -76,6 +76,7 @@ struct ChArgs {
   const T* phis;    // phi* (start of the sub-step), read pointwise
   T* acc;           // RK4 running sum phi* + sum b_i k_i
   T* out;           // next stage input or the new phi*
+  int adv;          // 1: convection u_hat . grad(phi); 0: div(phi u_hat)
 };
 
 // ---------------------------------------------------------------------------

@@ -90,6 +90,7 @@ int check_batch(const gpe_params* c, int count) {
   for (int i = 0; i < count; ++i) {
     if (c[i].geometry != GPE_GEOM_2D && c[i].geometry != GPE_GEOM_AXISYM) return GPE_EINVAL;
     if (c[i].geometry != c[0].geometry || c[i].precision != c[0].precision) return GPE_EINVAL;
+    if (c[i].ch_transport != GPE_CH_CONSERVATIVE) return GPE_EINVAL;
     if (gpe_workspace_bytes(&c[i]) == 0) return GPE_EINVAL;
   }
   return GPE_OK;

@@ -87,6 +87,10 @@ def test_ensemble_workspace_and_batch_validation(G):
     # header: 3 flow + 2 CH argument blocks per case, tiles, flags, tables
     assert total - sum(G.gpe_workspace_bytes(p) for p in P) < 1 << 20
     assert G.gpe_ensemble_workspace_bytes([]) == 0
+    # the batch kernels implement the conservative CH transport only
+    adv = G.params_from_problem(dict(W.ensemble_cases(2, seed=0)[0], ch_transport=1))
+    assert G.gpe_workspace_bytes(adv) > 0
+    assert G.gpe_ensemble_workspace_bytes([P[0], adv]) == 0
     mixed = [G.params_from_problem(dict(cases[0], precision="fp64"))] + P[1:]
     assert G.gpe_ensemble_workspace_bytes(mixed) == 0
     prob3, _ = W.rising_bubble_3d(nx=32, ny=32, nz=32, precision="fp32")

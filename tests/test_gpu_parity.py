@@ -141,6 +141,23 @@ def test_3d_lattices(gpe, oracle, lat):
     _check(prob, out, ref, 1e-11)
 
 
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_advective_ch_transport(gpe, oracle, name, precision):
+    """The CH convection as printed, u_hat . grad(phi) (ch_transport = 1)."""
+    prob, st = _case(name, seed=7, precision=precision)
+    prob["ch_transport"] = 1
+    nsteps = 40
+    _say(f"[parity] {name} {precision} advective CH n={prob['n']} steps={nsteps}")
+    ref = oracle.run(prob, st, nsteps)
+    out, d = _run_gpu(gpe, prob, st, nsteps)
+    assert d["finite"] == 1
+    if precision == "fp64":
+        _check(prob, out, ref, 1e-11)
+    else:
+        _check(prob, out, ref, 1e-4, keys=["p", "u", "phi"])
+
+
 def test_diagnostics_match_oracle(gpe, oracle):
     for name in CASES:
         prob, st = _case(name)
@@ -265,3 +282,26 @@ def test_full_size_256cubed_fp32_properties(gpe):
     assert np.max(np.abs(w - w[:, :, ::-1])) <= 1e-4 * sc
     assert np.max(np.abs(w - w[:, ::-1, :])) <= 1e-4 * sc
     assert np.max(np.abs(phi - phi[:, :, ::-1])) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# The paper's 3-D coalescence set-up (reduced: N_L = 12, 36^3 cells).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lat", [15, 19, 27])
+def test_coalescence_3d_against_oracle_and_symmetry(gpe, oracle, lat):
+    prob = W.coalescence_3d(n=36, lattice=lat, precision="fp64")
+    st = W.coalescence_state(prob)
+    _say(f"[parity] coalescence 36^3 D3Q{lat} fp64 20 steps")
+    s = gpe.Solver(prob, None)  # in-kernel initial drop
+    assert np.max(np.abs(s.get("phi") - st["phi"])) < 1e-14
+    s.run(20)
+    s.synchronize()
+    out = s.state()
+    s.close()
+    ref = oracle.run(prob, st, 20)
+    _check(prob, out, ref, 1e-11)
+    # the drop is centred on the y = 0 and z = 0 planes: the flow is
+    # symmetric under exchanging y and z (v <-> w)
+    tr = lambda a: np.transpose(a, (1, 0, 2))  # noqa: E731  (z, y, x) -> (y, z, x)
+    assert np.max(np.abs(out["phi"] - tr(out["phi"]))) < 1e-12
+    assert np.max(np.abs(out["v"] - tr(out["w"]))) < 1e-12 * max(1e-30, np.max(np.abs(out["v"])))

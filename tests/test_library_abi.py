@@ -92,6 +92,7 @@ def test_workspace_bytes(G):
     lambda P: setattr(P, "dt", 0.0),
     lambda P: setattr(P, "width", -1.0),
     lambda P: setattr(P, "rho_g", 0.0),
+    lambda P: setattr(P, "ch_transport", 2),    # only 0 (conservative) and 1 (advective)
 ])
 def test_invalid_params_rejected(G, mutate):
     prob, _ = W.static_drop_2d()

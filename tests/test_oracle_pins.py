@@ -388,6 +388,52 @@ def test_permutation_symmetry_3d(oracle):
 
 
 # ---------------------------------------------------------------------------
+# P10b: symmetry planes on every face are a periodic box of twice the size
+# holding the mirrored state (cell-centred fields even, the normal face
+# velocity odd and zero on the planes): same result to round-off, which pins
+# the ghost rules of symmetry planes, their edges and corners, on every field
+# and every stencil of both sub-steps (no body force: it is not mirror-symmetric)
+# ---------------------------------------------------------------------------
+def _mirror_extend(a, axis, normal):
+    a = np.moveaxis(a, axis, -1)
+    n = a.shape[-1]
+    out = np.zeros(a.shape[:-1] + (2 * n,))
+    out[..., :n] = a
+    if normal:  # face n + m mirrors face n - m with the sign flipped; face n is on the plane
+        out[..., n + 1:] = -a[..., 1:][..., ::-1]
+    else:
+        out[..., n:] = a[..., ::-1]
+    return np.moveaxis(out, -1, axis)
+
+
+@pytest.mark.parametrize("lat,transport", [(15, 0), (19, 1), (27, 0)])
+def test_symmetry_planes_equal_mirrored_periodic_box(oracle, lat, transport):
+    r = np.random.default_rng(lat)
+    nx, ny, nz = 6, 5, 4
+    prob = W.base_problem(dim=3, n=(nx, ny, nz), bc=(W.SYMMETRY,) * 6, lattice=lat, rho_l=1.0, rho_g=0.05,
+                          eta_l=0.05, eta_g=0.002, sigma=0.005, mob=0.02, width=3.0, ch_transport=transport)
+    st = W.zero_state(prob)
+    st["phi"] = np.tanh(r.normal(size=(nz, ny, nx)))
+    st["p"] = 1e-3 * r.normal(size=(nz, ny, nx))
+    for k in "uvw":
+        st[k] = 1e-2 * r.normal(size=(nz, ny, nx))
+    st["u"][:, :, 0] = 0.0
+    st["v"][:, 0, :] = 0.0
+    st["w"][0] = 0.0
+    big = {}
+    for k in ("p", "phi", "u", "v", "w"):
+        a = st[k]
+        for axis, face in ((2, "u"), (1, "v"), (0, "w")):
+            a = _mirror_extend(a, axis, k == face)
+        big[k] = a
+    pbig = dict(prob, n=(2 * nx, 2 * ny, 2 * nz), bc=(W.PERIODIC,) * 6)
+    a = oracle.run(prob, st, 3)
+    b = oracle.run(pbig, big, 3)
+    for k in ("p", "phi", "u", "v", "w"):
+        assert np.max(np.abs(a[k] - b[k][:nz, :ny, :nx])) <= 1e-14 * max(1.0, np.max(np.abs(a[k]))), k
+
+
+# ---------------------------------------------------------------------------
 # P11: axisymmetric Hagen-Poiseuille operator identity: the axial viscous
 # operator applied to u_z = r^2 returns 4 eta in every row off the wall,
 # including the axis row (face radius 0 closes the flux there)
