@@ -186,6 +186,37 @@ int gpe_run_n(gpe_state* s, int64_t n);
  * finite; *out is filled either way. */
 int gpe_diagnostics(gpe_state* s, gpe_diag* out);
 
+/* Experiment diagnostics (Sec. 4: the falling drop's centroid velocity
+ * U_drop and aspect ratio, the coalescing drops' radius R_r / half length
+ * R_x and centroid velocity, the Rayleigh-Taylor bubble and spike fronts).
+ * Positions are cell-centre coordinates in lattice units (cell i spans
+ * [i, i+1], its centre is i + 1/2); axes are those of gpe_params.n (2-D and
+ * axisymmetric: axis 0 = x or z, axis 1 = y or r; entries of a missing
+ * third axis are NaN).  FP64 reductions in a fixed order.  Each call
+ * synchronises the stream.  Returns GPE_OK, GPE_EINVAL or GPE_EHIP. */
+
+/* The liquid region, the cells with phi > 0, each weighted by w = r (its
+ * centre radius, axisymmetric geometry: integrals r dr dz per radian) or 1:
+ * out[0] = sum w, out[1..3] = its centroid sum w x / sum w per axis,
+ * out[4..6] = the mean of the cell-centre velocity (the mean of the cell's
+ * two faces) sum w u / sum w per axis.  out[1..6] are NaN if no cell has
+ * phi > 0. */
+int gpe_phase_stats(gpe_state* s, double out[7]);
+
+/* Extent of the interface along each axis a: over every pair of
+ * neighbouring cells along a (both inside the grid) whose phi lie on
+ * different sides of 0 (phi > 0 on exactly one), the crossing
+ * x_i + phi_i / (phi_i - phi_{i+1}) (linear between the centres);
+ * out[2a] = the smallest, out[2a+1] = the largest, NaN if there is none. */
+int gpe_interface_extent(gpe_state* s, double out[6]);
+
+/* The same crossings on one grid line parallel to axis `axis` (0 <= axis <
+ * dimension), through the cells whose indices along the other axes are
+ * (i0, i1) in increasing axis order (i1 = 0 in 2-D): out[0] = the first
+ * (smallest), out[1] = the last (largest), NaN if none.  GPE_EINVAL for an
+ * index outside the grid. */
+int gpe_line_crossings(gpe_state* s, int32_t axis, int32_t i0, int32_t i1, double out[2]);
+
 /* Copy one field between the device state and a host array of
  * n[0]*n[1]*n[2] doubles (converted from/to the state precision), in the
  * layout above.  GPE_FIELD_W is valid in 3-D only; for walls and symmetry

@@ -637,3 +637,117 @@ const char* gpe_strerror(int code) {
 }
 
 }  // extern "C"
+
+// ---- experiment diagnostics --------------------------------------------------
+namespace {
+
+template <typename T>
+gpe::PhaseArgs<T> phase_args(const gpe_state* s) {
+  gpe::PhaseArgs<T> a;
+  a.g = s->grid;
+  a.axisym = s->axi ? 1 : 0;
+  a.phi = buf<T>(s, B_PHI);
+  for (int q = 0; q < 4; ++q) a.q[q] = buf<T>(s, B_Q0 + q);
+  a.partial = buf<double>(s, B_SCR);
+  a.result = a.partial + gpe::kDiagBlocks * 8;
+  a.axis = 0;
+  a.idx[0] = a.idx[1] = a.idx[2] = 0;
+  return a;
+}
+
+// internal axis of problem axis a (2-D / axisymmetric grids are stored with
+// the second axis as internal Z); -1 if the problem has no such axis
+int internal_axis(const gpe_state* s, int a) {
+  if (s->dim == 3) return (a >= 0 && a < 3) ? a : -1;
+  return a == 0 ? 0 : (a == 1 ? 2 : -1);
+}
+
+int fetch_result(gpe_state* s, double out[8]) {
+  const double* res = buf<double>(s, B_SCR) + gpe::kDiagBlocks * 8;
+  if (hipMemcpyAsync(out, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+    return GPE_EHIP;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return GPE_EHIP;
+  return GPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpe_phase_stats(gpe_state* s, double out[7]) {
+  if (!s || !out) return GPE_EINVAL;
+  const hipError_t e = s->P.precision == GPE_FP64 ? gpe::launch_phase_stats<double>(phase_args<double>(s), s->stream)
+                                                  : gpe::launch_phase_stats<float>(phase_args<float>(s), s->stream);
+  if (e != hipSuccess) return GPE_EHIP;
+  double r[8];
+  const int rc = fetch_result(s, r);
+  if (rc) return rc;
+  out[0] = r[0];
+  for (int a = 0; a < 3; ++a) {
+    const int ia = internal_axis(s, a);
+    const bool ok = ia >= 0 && r[0] > 0.0;
+    out[1 + a] = ok ? r[1 + ia] / r[0] : NAN;
+    out[4 + a] = ok ? r[4 + ia] / r[0] : NAN;
+  }
+  return GPE_OK;
+}
+
+int gpe_interface_extent(gpe_state* s, double out[6]) {
+  if (!s || !out) return GPE_EINVAL;
+  const hipError_t e = s->P.precision == GPE_FP64
+                           ? gpe::launch_interface_extent<double>(phase_args<double>(s), s->stream)
+                           : gpe::launch_interface_extent<float>(phase_args<float>(s), s->stream);
+  if (e != hipSuccess) return GPE_EHIP;
+  double r[8];
+  const int rc = fetch_result(s, r);
+  if (rc) return rc;
+  for (int a = 0; a < 3; ++a) {
+    const int ia = internal_axis(s, a);
+    const bool ok = ia >= 0 && std::isfinite(r[2 * ia]) && std::isfinite(r[2 * ia + 1]);
+    out[2 * a] = ok ? -r[2 * ia] : NAN;
+    out[2 * a + 1] = ok ? r[2 * ia + 1] : NAN;
+  }
+  return GPE_OK;
+}
+
+int gpe_line_crossings(gpe_state* s, int32_t axis, int32_t i0, int32_t i1, double out[2]) {
+  if (!s || !out) return GPE_EINVAL;
+  const int ia = internal_axis(s, axis);
+  if (ia < 0) return GPE_EINVAL;
+  // the other problem axes in increasing order get i0, i1
+  int other[2], no = 0;
+  for (int a = 0; a < s->dim; ++a)
+    if (a != axis) other[no++] = a;
+  const int32_t iv[2] = {i0, i1};
+  int idx[3] = {0, 0, 0};
+  for (int q = 0; q < 2; ++q) {
+    if (q >= no) {
+      if (iv[q] != 0) return GPE_EINVAL;
+      continue;
+    }
+    const int io = internal_axis(s, other[q]);
+    if (iv[q] < 0 || iv[q] >= s->grid.n[io]) return GPE_EINVAL;
+    idx[io] = iv[q];
+  }
+  hipError_t e;
+  if (s->P.precision == GPE_FP64) {
+    gpe::PhaseArgs<double> a = phase_args<double>(s);
+    a.axis = ia;
+    for (int d = 0; d < 3; ++d) a.idx[d] = idx[d];
+    e = gpe::launch_line_crossings<double>(a, s->stream);
+  } else {
+    gpe::PhaseArgs<float> a = phase_args<float>(s);
+    a.axis = ia;
+    for (int d = 0; d < 3; ++d) a.idx[d] = idx[d];
+    e = gpe::launch_line_crossings<float>(a, s->stream);
+  }
+  if (e != hipSuccess) return GPE_EHIP;
+  double r[8];
+  const int rc = fetch_result(s, r);
+  if (rc) return rc;
+  out[0] = std::isfinite(r[0]) ? -r[0] : NAN;
+  out[1] = std::isfinite(r[1]) ? r[1] : NAN;
+  return GPE_OK;
+}
+
+}  // extern "C"

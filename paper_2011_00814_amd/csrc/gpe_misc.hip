@@ -151,6 +151,175 @@ __global__ __launch_bounds__(64) void diag_final_kernel(const double* partial, i
     for (int s = 0; s < 8; ++s) out[s] = r[s];
 }
 
+// ---------------------------------------------------------------------------
+// Experiment diagnostics (Sec. 4: the falling drop's centroid velocity and
+// aspect ratio, the coalescing drops' radius / half length and centroid
+// velocity, the Rayleigh-Taylor fronts).
+// ---------------------------------------------------------------------------
+
+// centre value of face component ax at cell (i, j, k): mean of its low and
+// high faces, the high face by the ghost rule of the boundary it may lie on
+template <typename T>
+__device__ __forceinline__ double centre_velocity(const Grid& g, const T* u, int ax, int i, int j, int k) {
+  const int nx = g.n[0], ny = g.n[1];
+  const double lo = (double)u[((size_t)k * ny + j) * nx + i];
+  int hi[3] = {i, j, k};
+  int sgn;
+  hi[ax] = map_face(hi[ax] + 1, g.n[ax], g.bc[2 * ax], sgn);
+  const double up = sgn * (double)u[((size_t)hi[2] * ny + hi[1]) * nx + hi[0]];
+  return 0.5 * (lo + up);
+}
+
+// slots over the cells with phi > 0, weight w = r = k + 1/2 (axisymmetric)
+// or 1: 0 sum w, 1-3 sum w x_c (internal X, Y, Z), 4-6 sum w u_c
+template <typename T>
+__global__ __launch_bounds__(256) void phase_stats_kernel(PhaseArgs<T> a) {
+  const Grid& g = a.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const size_t ncell = (size_t)nx * ny * nz;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (size_t)gridDim.x * blockDim.x) {
+    if (!((double)a.phi[c] > 0.0)) continue;
+    const int i = (int)(c % nx);
+    const int j = (int)((c / nx) % ny);
+    const int k = (int)(c / ((size_t)nx * ny));
+    const double w = a.axisym ? (k + 0.5) : 1.0;
+    acc[0] += w;
+    acc[1] += w * (i + 0.5);
+    acc[2] += w * (j + 0.5);
+    acc[3] += w * (k + 0.5);
+    for (int ax = 0; ax < 3; ++ax)
+      if (a.q[1 + ax]) acc[4 + ax] += w * centre_velocity(g, a.q[1 + ax], ax, i, j, k);
+  }
+  __shared__ double red[4][7];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  for (int s = 0; s < 7; ++s) {
+    const double r = wave_sum(acc[s]);
+    if (lane == 0) red[wv][s] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < 7; ++s) {
+      double o = red[0][s];
+      for (int w = 1; w < (int)(blockDim.x / 64); ++w) o += red[w][s];
+      a.partial[(size_t)blockIdx.x * 8 + s] = o;
+    }
+    a.partial[(size_t)blockIdx.x * 8 + 7] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(64) void sum8_final_kernel(const double* partial, int nblk, double* out) {
+  const int l = threadIdx.x;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = l; b < nblk; b += 64)
+    for (int s = 0; s < 8; ++s) acc[s] += partial[(size_t)b * 8 + s];
+  for (int s = 0; s < 8; ++s) {
+    const double r = wave_sum(acc[s]);
+    if (l == 0) out[s] = r;
+  }
+}
+
+// phi = 0 crossing between cell c (coordinate x0 = index + 1/2) and its
+// neighbour one cell further along the axis, by linear interpolation
+__device__ __forceinline__ bool crossing(double f0, double f1, double x0, double& pos) {
+  if ((f0 > 0.0) == (f1 > 0.0)) return false;
+  pos = x0 + f0 / (f0 - f1);
+  return true;
+}
+
+// slots 2a / 2a+1: smallest / largest crossing along internal axis a, over
+// all neighbour pairs inside the grid (smallest stored negated as a max)
+template <typename T>
+__global__ __launch_bounds__(256) void interface_extent_kernel(PhaseArgs<T> a) {
+  const Grid& g = a.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const size_t ncell = (size_t)nx * ny * nz;
+  const size_t stride[3] = {1, (size_t)nx, (size_t)nx * ny};
+  double acc[6] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int idx[3] = {(int)(c % nx), (int)((c / nx) % ny), (int)(c / ((size_t)nx * ny))};
+    const double f0 = (double)a.phi[c];
+    for (int ax = 0; ax < 3; ++ax) {
+      if (idx[ax] + 1 >= g.n[ax]) continue;
+      double pos;
+      if (crossing(f0, (double)a.phi[c + stride[ax]], idx[ax] + 0.5, pos)) {
+        acc[2 * ax] = fmax(acc[2 * ax], -pos);
+        acc[2 * ax + 1] = fmax(acc[2 * ax + 1], pos);
+      }
+    }
+  }
+  __shared__ double red[4][6];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  for (int s = 0; s < 6; ++s) {
+    const double r = wave_max(acc[s]);
+    if (lane == 0) red[wv][s] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < 6; ++s) {
+      double o = red[0][s];
+      for (int w = 1; w < (int)(blockDim.x / 64); ++w) o = fmax(o, red[w][s]);
+      a.partial[(size_t)blockIdx.x * 8 + s] = o;
+    }
+    a.partial[(size_t)blockIdx.x * 8 + 6] = -INFINITY;
+    a.partial[(size_t)blockIdx.x * 8 + 7] = -INFINITY;
+  }
+}
+
+__global__ __launch_bounds__(64) void max8_final_kernel(const double* partial, int nblk, double* out) {
+  const int l = threadIdx.x;
+  double acc[8];
+  for (int s = 0; s < 8; ++s) acc[s] = -INFINITY;
+  for (int b = l; b < nblk; b += 64)
+    for (int s = 0; s < 8; ++s) acc[s] = fmax(acc[s], partial[(size_t)b * 8 + s]);
+  for (int s = 0; s < 8; ++s) {
+    const double r = wave_max(acc[s]);
+    if (l == 0) out[s] = r;
+  }
+}
+
+// one work-group: first and last crossing along the line parallel to
+// internal axis a.axis through a.idx (the axis' own entry ignored);
+// result[0] = -first, result[1] = last (-inf if none)
+template <typename T>
+__global__ __launch_bounds__(256) void line_crossings_kernel(PhaseArgs<T> a) {
+  const Grid& g = a.g;
+  const int ax = a.axis, n = g.n[ax];
+  const size_t stride[3] = {1, (size_t)g.n[0], (size_t)g.n[0] * g.n[1]};
+  size_t base = 0;
+  for (int d = 0; d < 3; ++d)
+    if (d != ax) base += (size_t)a.idx[d] * stride[d];
+  double lo = -INFINITY, hi = -INFINITY;
+  for (int t = (int)threadIdx.x; t + 1 < n; t += (int)blockDim.x) {
+    double pos;
+    const size_t c = base + (size_t)t * stride[ax];
+    if (crossing((double)a.phi[c], (double)a.phi[c + stride[ax]], t + 0.5, pos)) {
+      lo = fmax(lo, -pos);
+      hi = fmax(hi, pos);
+    }
+  }
+  __shared__ double red[4][2];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  lo = wave_max(lo);
+  hi = wave_max(hi);
+  if (lane == 0) {
+    red[wv][0] = lo;
+    red[wv][1] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double l0 = red[0][0], h0 = red[0][1];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
+      l0 = fmax(l0, red[w][0]);
+      h0 = fmax(h0, red[w][1]);
+    }
+    a.result[0] = l0;
+    a.result[1] = h0;
+  }
+}
+
 template <typename T>
 hipError_t launch_init(const InitArgs<T>& a, hipStream_t s) {
   const size_t ncell = (size_t)a.n[0] * a.n[1] * a.n[2];
@@ -168,6 +337,36 @@ hipError_t launch_diag(const DiagArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_phase_stats(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((phase_stats_kernel<T>), dim3(kDiagBlocks), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum8_final_kernel, dim3(1), dim3(64), 0, s, a.partial, kDiagBlocks, a.result);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interface_extent(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((interface_extent_kernel<T>), dim3(kDiagBlocks), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(max8_final_kernel, dim3(1), dim3(64), 0, s, a.partial, kDiagBlocks, a.result);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_line_crossings(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((line_crossings_kernel<T>), dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_phase_stats<float>(const PhaseArgs<float>&, hipStream_t);
+template hipError_t launch_phase_stats<double>(const PhaseArgs<double>&, hipStream_t);
+template hipError_t launch_interface_extent<float>(const PhaseArgs<float>&, hipStream_t);
+template hipError_t launch_interface_extent<double>(const PhaseArgs<double>&, hipStream_t);
+template hipError_t launch_line_crossings<float>(const PhaseArgs<float>&, hipStream_t);
+template hipError_t launch_line_crossings<double>(const PhaseArgs<double>&, hipStream_t);
 template hipError_t launch_init<float>(const InitArgs<float>&, hipStream_t);
 template hipError_t launch_init<double>(const InitArgs<double>&, hipStream_t);
 template hipError_t launch_diag<float>(const DiagArgs<float>&, hipStream_t);

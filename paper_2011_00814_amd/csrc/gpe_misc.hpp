@@ -32,8 +32,27 @@ struct DiagArgs {
   double* result;    // 8
 };
 
+// Liquid-region moments and interface crossings (the experiment diagnostics)
+template <typename T>
+struct PhaseArgs {
+  Grid g;
+  int axisym;
+  const T* phi;
+  const T* q[4];     // p, uX, uY (null in 2-D), uZ
+  double* partial;   // kDiagBlocks x 8
+  double* result;    // 8
+  // line crossings: internal axis and the indices of the two other axes
+  int axis, idx[3];
+};
+
 template <typename T>
 hipError_t launch_init(const InitArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_phase_stats(const PhaseArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_interface_extent(const PhaseArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_line_crossings(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_diag(const DiagArgs<T>& a, hipStream_t s);
 

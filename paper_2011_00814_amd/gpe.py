@@ -93,6 +93,13 @@ def lib():
         L.gpe_run_n.restype = ctypes.c_int
         L.gpe_diagnostics.argtypes = [vp, ctypes.POINTER(gpe_diag)]
         L.gpe_diagnostics.restype = ctypes.c_int
+        d7 = ctypes.POINTER(ctypes.c_double)
+        L.gpe_phase_stats.argtypes = [vp, d7]
+        L.gpe_phase_stats.restype = ctypes.c_int
+        L.gpe_interface_extent.argtypes = [vp, d7]
+        L.gpe_interface_extent.restype = ctypes.c_int
+        L.gpe_line_crossings.argtypes = [vp, i32, i32, i32, d7]
+        L.gpe_line_crossings.restype = ctypes.c_int
         L.gpe_copy_field.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, sz]
         L.gpe_copy_field.restype = ctypes.c_int
         L.gpe_field_offset.argtypes = [vp, ctypes.c_int]
@@ -175,6 +182,34 @@ def gpe_diagnostics(h, check=True) -> dict:
     if rc and (check or rc != GPE_ENONFINITE):
         raise GpeError(rc, "gpe_diagnostics")
     return {k: getattr(d, k) for k, _ in gpe_diag._fields_ if k != "reserved"}
+
+
+def gpe_phase_stats(h) -> dict:
+    """Liquid region (phi > 0): weighted volume, centroid and mean centre
+    velocity per axis (NaN where undefined)."""
+    out = (ctypes.c_double * 7)()
+    rc = lib().gpe_phase_stats(h, out)
+    if rc:
+        raise GpeError(rc, "gpe_phase_stats")
+    return {"volume": out[0], "centroid": tuple(out[1:4]), "velocity": tuple(out[4:7])}
+
+
+def gpe_interface_extent(h) -> list:
+    """[(smallest, largest) phi = 0 crossing] per axis (NaN if none)."""
+    out = (ctypes.c_double * 6)()
+    rc = lib().gpe_interface_extent(h, out)
+    if rc:
+        raise GpeError(rc, "gpe_interface_extent")
+    return [(out[2 * a], out[2 * a + 1]) for a in range(3)]
+
+
+def gpe_line_crossings(h, axis: int, i0: int, i1: int = 0) -> tuple:
+    """(first, last) phi = 0 crossing on one grid line (NaN if none)."""
+    out = (ctypes.c_double * 2)()
+    rc = lib().gpe_line_crossings(h, int(axis), int(i0), int(i1), out)
+    if rc:
+        raise GpeError(rc, "gpe_line_crossings")
+    return out[0], out[1]
 
 
 def gpe_copy_field(h, field: int, direction: int, host: np.ndarray):
@@ -313,6 +348,15 @@ class _Grid:
 
     def diagnostics(self, check=True) -> dict:
         return gpe_diagnostics(self.h, check)
+
+    def phase_stats(self) -> dict:
+        return gpe_phase_stats(self.h)
+
+    def interface_extent(self) -> list:
+        return gpe_interface_extent(self.h)
+
+    def line_crossings(self, axis: int, i0: int, i1: int = 0) -> tuple:
+        return gpe_line_crossings(self.h, axis, i0, i1)
 
     def get(self, key: str) -> np.ndarray:
         out = np.empty(self.shape, dtype=np.float64)

@@ -332,3 +332,107 @@ def coalescence_state(prob) -> dict:
     st = zero_state(prob)
     st["phi"] = -np.tanh(2.0 * (r - ini["radius"]) / ini["width"])
     return st
+
+
+# --------------------------------------------------------------------------
+# The paper's experiments (Sec. 4), in lattice units: L_c = N_L cells,
+# T_c = N_t steps (dx = dt = 1, U_c = N_L / N_t, c_s^2 = 1/3), sigma_ref = 1.
+# Each returns (prob, state, scales): `scales` holds the length, velocity
+# and time units the paper reports its diagnostics in.
+# --------------------------------------------------------------------------
+def falling_drop_axisym(NL=50, precision="fp64", ch_transport=0):
+    """Falling drop (Sec. 4): axisymmetric [0, 24 R] x [0, 8 R] (z, r) with
+    L_c = R; the axis r = 0 is a symmetry line, the other three sides are
+    no-slip walls; r_rho = 1.15, r_eta = 1, Eo = g (rho_L - rho_G) D^2 /
+    sigma = 144, Oh = eta_L / sqrt(rho_L D sigma) = 0.0466 (D = 2R) with
+    U_c = sigma / eta_L; N_t = 80 N_L (c = 80), Cn = 0.06, Pe = 1000; gravity
+    along +z on the drop only (rho_ref = rho_G); drop centred at (2R, 0).
+    Reported in U_c' = sqrt(g D), T_c' = sqrt(D / g)."""
+    Nt = 80.0 * NL
+    Uc = NL / Nt
+    D = 2.0 * NL
+    Oh, Eo, r_rho = 0.0466, 144.0, 1.15
+    eta_l = Oh * Oh * D * Uc          # Oh^2 = eta_L^2 / (D sigma), sigma = U_c eta_L
+    sigma = Uc * eta_l
+    rho_g = 1.0 / r_rho
+    g = Eo * sigma / ((1.0 - rho_g) * D * D)
+    W = 0.06 * NL
+    prob = base_problem(
+        dim=2, n=(int(24 * NL), int(8 * NL), 1), bc=(WALL, WALL, SYMMETRY, WALL, 0, 0),
+        rho_l=1.0, rho_g=rho_g, eta_l=eta_l, eta_g=eta_l, sigma=sigma, mob=Uc * NL * NL / 1000.0,
+        width=W, g=(g, 0.0, 0.0), rho_ref=rho_g, precision=precision, ch_transport=ch_transport)
+    prob["axisym"] = 1
+    x, y, _ = _centres(prob)
+    r = np.sqrt((x - 2.0 * NL) ** 2 + y ** 2)
+    st = zero_state(prob)
+    st["phi"] = -np.tanh(2.0 * (r - NL) / W)
+    scales = {"L": float(NL), "U": math.sqrt(g * D), "T": math.sqrt(D / g), "D": D}
+    return prob, st, scales
+
+
+def coalescence_axisym(NL=40, Oh=0.119, precision="fp64", N_t=None):
+    """Axisymmetric drop coalescence (Sec. 4): [0, 3 R] x [0, 3 R] (z, r),
+    symmetry on all sides, drop of radius R = L_c centred at (R, 0) touching
+    its mirror image at z = 0; r_rho = 50, r_eta = 58.8, Oh = eta_L /
+    sqrt(rho_L sigma R) with U_c = sigma / eta_L, N_t = 10 N_L (50 N_L for
+    Oh = 0.3), Cn = 0.1, Pe = 8e3; advective CH transport (light gas).
+    Reported in U_ci = sqrt(sigma / (rho_L R)), T_ci = R / U_ci."""
+    Nt = float(N_t) if N_t else (50.0 if Oh >= 0.3 else 10.0) * NL
+    Uc = NL / Nt
+    eta_l = Uc * NL * Oh * Oh          # Oh^2 = eta_L / (U_c R) with sigma = U_c eta_L
+    sigma = Uc * eta_l
+    W = 0.1 * NL
+    prob = base_problem(
+        dim=2, n=(int(3 * NL), int(3 * NL), 1), bc=(SYMMETRY,) * 4 + (0, 0),
+        rho_l=1.0, rho_g=1.0 / 50.0, eta_l=eta_l, eta_g=eta_l / 58.8, sigma=sigma,
+        mob=Uc * NL * NL / 8e3, width=W, precision=precision, ch_transport=1)
+    prob["axisym"] = 1
+    x, y, _ = _centres(prob)
+    r = np.sqrt((x - NL) ** 2 + y ** 2)
+    st = zero_state(prob)
+    st["phi"] = -np.tanh(2.0 * (r - NL) / W)
+    Uci = math.sqrt(sigma / NL)
+    scales = {"L": float(NL), "U": Uci, "T": NL / Uci}
+    return prob, st, scales
+
+
+def coalescence_3d_replay(NL=40, Oh=0.119, lattice=19, precision="fp64"):
+    """The 3-D coalescence (Sec. 4) as a replay: the set-up of coalescence_3d
+    with the host-built initial field, reported in U_ci, T_ci like the
+    axisymmetric case.  D3Q19 by default: with D3Q15 the paper's parameters
+    lie beyond the RK4 stability limit of the CH sub-step."""
+    prob = coalescence_3d(n=int(3 * NL), Oh=Oh, lattice=lattice, precision=precision)
+    prob = dict(prob)
+    prob.pop("init")
+    st = coalescence_state(dict(prob, init={"center": (NL, 0.0, 0.0), "radius": float(NL),
+                                            "width": prob["width"]}))
+    Uci = math.sqrt(prob["sigma"] / NL)
+    scales = {"L": float(NL), "U": Uci, "T": NL / Uci}
+    return prob, st, scales
+
+
+def rt_paper(NL=256, Re=256.0, precision="fp64", ch_transport=0):
+    """Rayleigh-Taylor instability as the paper sets it up (Sec. 4): the lower
+    half [0, 4] x [0, 1/2] of the domain in L_c = L_y = lambda, no-slip walls
+    at x = 0 and 4, symmetry at y = 0 and 1/2; At = 0.5 (r_rho = 3); Re = 256
+    with r_eta = 3 (r_nu = 1) or Re = 3000 with r_eta = 1; U_c = sqrt(lambda
+    g), N_t = 200 N_L (c = 200), Cn = 1/64, Pe = 8e4, sigma = 0; liquid on the
+    left of x = h(y) = 2 + 0.1 cos(2 pi (y + 1/2)), gravity along +x on the
+    liquid (rho_ref = rho_G).  Reported in L_c, U_c, T_c."""
+    Nt = 200.0 * NL
+    Uc = NL / Nt
+    g = Uc * Uc / NL
+    r_eta = 3.0 if Re < 1000 else 1.0
+    eta_l = Uc * NL / Re
+    W = NL / 64.0
+    prob = base_problem(
+        dim=2, n=(int(4 * NL), int(NL // 2), 1), bc=(WALL, WALL, SYMMETRY, SYMMETRY, 0, 0),
+        rho_l=1.0, rho_g=1.0 / 3.0, eta_l=eta_l, eta_g=eta_l / r_eta, sigma=0.0,
+        mob=Uc * NL * NL / 8e4, width=W, g=(g, 0.0, 0.0), rho_ref=1.0 / 3.0, precision=precision,
+        ch_transport=ch_transport)
+    x, y, _ = _centres(prob)
+    h = (2.0 + 0.1 * np.cos(2.0 * math.pi * (y / NL + 0.5))) * NL
+    st = zero_state(prob)
+    st["phi"] = -np.tanh(2.0 * (x - h) / W)
+    scales = {"L": float(NL), "U": Uc, "T": Nt}
+    return prob, st, scales

@@ -23,7 +23,7 @@ def G():
 
 def test_exports_every_header_symbol(G):
     names = G.header_functions()
-    assert len(names) == 20
+    assert len(names) == 23
     L = G.lib()
     for n in names:
         assert hasattr(L, n), n
