@@ -1,0 +1,126 @@
+"""Replays of the paper's experiments (Sec. 4) on the GPU with the paper's
+diagnostics, computed by the library's reduction kernels:
+
+- falling drop (axisymmetric, Eo 144, Oh 0.0466): centroid velocity U_drop
+  and aspect ratio Th / Wh (axial thickness over radial width), in
+  U_c' = sqrt(g D), T_c' = sqrt(D / g);
+- axisymmetric and 3-D coalescence (r_rho 50, r_eta 58.8): the radius R_r of
+  the liquid bridge at z = 0 (axisymmetric) or the half length R_x of the
+  drop on the x axis (3-D), and the centroid velocity of the drop in the box
+  (along the line of centres in the axisymmetric case, across it in 3-D),
+  in R, U_ci, T_ci; each case also records the other's length (the 3-D
+  bridge radius on x = 0, the axisymmetric half length on the axis), so that
+  the two geometries can be compared on the same flow;
+- Rayleigh-Taylor (At 0.5, Re 256 / 3000): bubble front (smallest crossing
+  on y = 0) and spike front (largest crossing on y = 1/2), in L_c, T_c.
+
+Run `python -m paper_2011_00814_amd.replays [names] --out FILE`; each case
+prints one JSON line with its time series.  The paper gives these curves as
+figures only, so the series are self-consistency and regression data.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+from . import gpe as G
+from . import workloads as W
+
+
+def _falling(prec):
+    return W.falling_drop_axisym(precision=prec)
+
+
+CASES = {
+    # name: (builder(precision) -> (prob, state, scales), end time in the case's time unit, outputs)
+    "falling_drop": (_falling, 12.0, 24),
+    "coalescence_axisym_oh0.037": (lambda p: W.coalescence_axisym(Oh=0.037, precision=p), 4.0, 20),
+    "coalescence_axisym_oh0.119": (lambda p: W.coalescence_axisym(Oh=0.119, precision=p), 4.0, 20),
+    "coalescence_axisym_oh0.3": (lambda p: W.coalescence_axisym(Oh=0.3, precision=p), 4.0, 20),
+    "coalescence_3d_oh0.119": (lambda p: W.coalescence_3d_replay(Oh=0.119, precision=p), 4.0, 20),
+    "rt_re256": (lambda p: W.rt_paper(Re=256.0, precision=p), 4.5, 18),
+    "rt_re3000": (lambda p: W.rt_paper(Re=3000.0, precision=p), 3.5, 14),
+}
+
+
+def observe(name: str, s: G.Solver, prob: dict, sc: dict) -> dict:
+    """The paper's diagnostics of case `name` for the current state of s."""
+    st = s.phase_stats()
+    out = {"volume": st["volume"]}
+    if name == "falling_drop":
+        ext = s.interface_extent()
+        out["U_drop"] = st["velocity"][0] / sc["U"]
+        out["z_c"] = st["centroid"][0] / sc["L"]
+        out["aspect"] = (ext[0][1] - ext[0][0]) / (2.0 * ext[1][1])
+    elif name.startswith("coalescence_axisym"):
+        out["R_r"] = s.line_crossings(1, 0)[1] / sc["L"]
+        out["U_drop"] = st["velocity"][0] / sc["U"]
+        # half length on the axis: the 3-D case's R_x
+        out["R_axis"] = s.line_crossings(0, 0)[1] / sc["L"]
+    elif name.startswith("coalescence_3d"):
+        out["R_x"] = s.line_crossings(0, 0, 0)[1] / sc["L"]
+        out["W_drop"] = st["velocity"][2] / sc["U"]
+        # bridge radius on the contact plane x = 0 (along y at z = 0): the
+        # axisymmetric case's R_r
+        out["R_neck"] = s.line_crossings(1, 0, 0)[1] / sc["L"]
+    elif name.startswith("rt"):
+        ny = prob["n"][1]
+        out["bubble"] = s.line_crossings(0, 0)[0] / sc["L"]
+        out["spike"] = s.line_crossings(0, ny - 1)[1] / sc["L"]
+    return out
+
+
+def run(name: str, precision: str = "fp64", t_end: float | None = None, n_out: int | None = None,
+        device: str = "cuda:0") -> dict:
+    build, t_def, n_def = CASES[name]
+    prob, state, sc = build(precision)
+    t_end = t_def if t_end is None else t_end
+    n_out = n_def if n_out is None else n_out
+    total = int(round(t_end * sc["T"]))
+    s = G.Solver(prob, state, device=device)
+    nx, ny, nz = prob["n"]
+    series = [dict(t=0.0, **observe(name, s, prob, sc))]
+    vol0 = series[0]["volume"]
+    done, wall = 0, 0.0
+    for q in range(1, n_out + 1):
+        target = total * q // n_out
+        t0 = time.perf_counter()
+        s.run(target - done)
+        s.synchronize()
+        wall += time.perf_counter() - t0
+        done = target
+        d = s.diagnostics(check=False)
+        row = dict(t=done / sc["T"], **observe(name, s, prob, sc))
+        row["finite"] = d["finite"]
+        series.append(row)
+        if not d["finite"]:
+            break
+    s.close()
+    for row in series:
+        row["volume"] = row["volume"] / vol0 if vol0 else math.nan
+    return {"case": name, "precision": precision, "grid": list(prob["n"]), "steps": done,
+            "steps_per_time_unit": sc["T"], "wall_s": round(wall, 3),
+            "mlups": round(nx * ny * nz * done / max(wall, 1e-9) / 1e6, 1), "series": series}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="*", default=list(CASES))
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"))
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    G.lib()
+    results = []
+    for name in args.names:
+        r = run(name, args.precision)
+        results.append(r)
+        print(json.dumps(r), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(results, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

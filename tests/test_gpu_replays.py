@@ -1,0 +1,144 @@
+"""The paper's experiments on the GPU (marked gpu): the diagnostics kernels
+against their CPU reference on GPU-produced states, reduced-size replays
+against the oracle, and the first stretch of each full-size replay.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2011_00814_amd import workloads as W
+from tests.parity_util import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpe():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_00814_amd import gpe as G
+
+    G.lib()
+    return G
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+SMALL = {
+    "falling_drop": lambda prec: W.falling_drop_axisym(NL=10, precision=prec),
+    "coalescence_axisym": lambda prec: W.coalescence_axisym(NL=12, precision=prec),
+    "coalescence_3d": lambda prec: W.coalescence_3d_replay(NL=10, precision=prec),
+    "rt_re256": lambda prec: W.rt_paper(NL=32, precision=prec),
+}
+
+
+def _diag_ref(prob, st):
+    from oracle import diag_oracle as D
+
+    vol, c, v = D.phase_stats(prob, st)
+    ext = D.interface_extent(prob, st)
+    return vol, c, v, ext
+
+
+def _close(a, b, tol):
+    return (math.isnan(a) and math.isnan(b)) or abs(a - b) <= tol * max(1.0, abs(b))
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_diagnostics_kernels_match_reference(gpe, name, precision):
+    from oracle import diag_oracle as D
+
+    prob, st, sc = SMALL[name](precision)
+    _say(f"[replay diag] {name} {precision} n={prob['n']}")
+    s = gpe.Solver(prob, st)
+    s.run(30)
+    s.synchronize()
+    cur = s.state()  # the GPU's own state, converted to FP64
+    vol, c, v, ext = _diag_ref(prob, cur)
+    ps = s.phase_stats()
+    got_ext = s.interface_extent()
+    assert _close(ps["volume"], vol, 1e-13)
+    for a in range(3):
+        assert _close(ps["centroid"][a], c[a], 1e-12) and _close(ps["velocity"][a], v[a], 1e-10), a
+        for q in range(2):
+            assert _close(got_ext[a][q], ext[a][q], 1e-12), (a, q)
+    dim = prob["dim"]
+    for axis in range(dim):
+        n_other = [prob["n"][b] for b in range(dim) if b != axis]
+        for i0 in (0, n_other[0] // 2, n_other[0] - 1):
+            i1 = 0 if dim == 2 else n_other[1] // 3
+            ref = D.line_crossings(prob, cur, axis, i0, i1)
+            got = s.line_crossings(axis, i0, i1)
+            assert _close(got[0], ref[0], 1e-12) and _close(got[1], ref[1], 1e-12), (axis, i0, i1)
+    with pytest.raises(gpe.GpeError):
+        s.line_crossings(0, prob["n"][1], 0)  # index beyond the grid
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_reduced_replays_match_oracle(gpe, oracle, name):
+    prob, st, sc = SMALL[name]("fp64")
+    nsteps = 60
+    _say(f"[replay parity] {name} n={prob['n']} steps={nsteps}")
+    ref = oracle.run(prob, st, nsteps)
+    s = gpe.Solver(prob, st)
+    s.run(nsteps)
+    s.synchronize()
+    out = s.state()
+    s.close()
+    errs = compare_states(prob, out, ref)
+    assert all(e <= 1e-11 for e in errs.values()), errs
+
+
+@pytest.mark.parametrize("name,frac", [("falling_drop", 0.1), ("coalescence_axisym_oh0.119", 0.1),
+                                       ("coalescence_3d_oh0.119", 0.05), ("rt_re256", 0.1)])
+def test_full_size_replay_start(gpe, name, frac):
+    from paper_2011_00814_amd import replays as R
+
+    _say(f"[replay full] {name} first {frac} of the run")
+    t_end = R.CASES[name][1] * frac
+    r = R.run(name, "fp64", t_end=t_end, n_out=4)
+    ser = r["series"]
+    assert all(row.get("finite", 1) == 1 for row in ser)
+    assert all(abs(row["volume"] - 1.0) < 0.02 for row in ser), [row["volume"] for row in ser]
+    if name == "falling_drop":
+        # the drop accelerates from rest along +z and stays nearly spherical
+        u = [row["U_drop"] for row in ser]
+        assert u[0] == 0.0 and all(b > a for a, b in zip(u[1:], u[2:])) and u[-1] > 0.03
+        assert all(abs(row["aspect"] - 1.0) < 0.1 for row in ser)
+    elif name.startswith("coalescence_axisym"):
+        rr = [row["R_r"] for row in ser]
+        assert all(b > a for a, b in zip(rr, rr[1:]))       # the bridge widens
+    elif name.startswith("coalescence_3d"):
+        rx = [row["R_x"] for row in ser]
+        assert rx[-1] < rx[0] <= 2.0 + 1e-9                 # the merged drop shortens along x
+    else:
+        assert ser[-1]["spike"] > ser[0]["spike"] and ser[-1]["bubble"] < ser[0]["bubble"]
+
+
+def test_axisymmetric_and_3d_coalescence_agree(gpe):
+    """The same coalescence computed in axisymmetric geometry (D2Q9 CH
+    stencils, cylindrical terms) and in 3-D (D3Q19, one eighth of the
+    domain): the bridge radius and the half length along the line of
+    centres agree over the whole run."""
+    from paper_2011_00814_amd import replays as R
+
+    _say("[replay cross] coalescence axisymmetric vs 3-D, t <= 4 T_ci")
+    a = R.run("coalescence_axisym_oh0.119", "fp64", t_end=4.0, n_out=8)["series"]
+    b = R.run("coalescence_3d_oh0.119", "fp64", t_end=4.0, n_out=8)["series"]
+    assert len(a) == len(b) == 9
+    for ra, rb in zip(a[1:], b[1:]):
+        # measured: within 0.002 R (bridge) and 0.004 R (half length)
+        assert abs(ra["R_r"] - rb["R_neck"]) < 0.01, (ra, rb)
+        assert abs(ra["R_axis"] - rb["R_x"]) < 0.01, (ra, rb)
+    # the drops merge: the half length falls from 2 R below the radius of
+    # the merged drop, 2^(1/3) R, during the first oscillation
+    assert min(r["R_x"] for r in b) < 2 ** (1 / 3)
