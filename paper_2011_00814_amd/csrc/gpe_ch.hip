@@ -24,10 +24,11 @@
 
 namespace gpe {
 
-// Occupancy target: 4 waves per SIMD in FP32 (<= 128 VGPRs, which the LDS
-// footprint of two work-groups per CU matches); FP64 is LDS-limited to 2.
+// Occupancy target: 6 waves per SIMD in FP32 (<= 80 VGPRs; three
+// work-groups of 512 threads per CU fit the LDS footprint below); FP64 is
+// LDS-limited to 2.
 template <typename T>
-struct ChOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 2; };
+struct ChOcc { static constexpr int W = sizeof(T) == 4 ? 6 : 2; };
 
 // One work-group tile (btx, bty) x Z chunk btz of the grid described by A.
 template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY, bool ADV>
@@ -37,11 +38,18 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   constexpr int PY = (DIM == 3) ? TY + 4 : 1;
   constexpr int PLANE = PX * PY;
   constexpr int EY = (DIM == 3) ? PX : 0;
-  // 3-slot rings (slot of plane m = (m - z0) mod 3): phi, Z face sums, mu,
-  // and the flux components; single slots: X / Y face sums of one plane
-  constexpr int S_PH = 0, S_SZ = 3, S_MU = 6, S_FX = 9, S_FY = 12, S_FZ = 15;
-  constexpr int S_SX = 18, S_SY = 19, NSLOT = 20;
+  // mu and the flux components live on [-1, T] only: a tighter plane
+  constexpr int QX = TX + 2;
+  constexpr int QY = (DIM == 3) ? TY + 2 : 1;
+  constexpr int QPLANE = QX * QY;
+  constexpr int QEY = (DIM == 3) ? QX : 0;
+  // 3-slot rings (slot of plane m = (m - z0) mod 3) of phi and the Z face
+  // sums, single slots of the X / Y face sums of one plane (halo'd plane);
+  // 3-slot rings of mu and the flux components (tight plane)
+  constexpr int S_PH = 0, S_SZ = 3, S_SX = 6, S_SY = 7, NSLOT = 8;
+  constexpr int S_MU = 0, S_FX = 3, S_FY = 6, S_FZ = 9, NQSLOT = 12;
   __shared__ T lds[NSLOT * PLANE];
+  __shared__ T ldq[NQSLOT * QPLANE];
 
   const Grid& g = A.g;
   const Consts<T>& c = A.c;
@@ -55,6 +63,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   const int ij = j * nx + i;  // in-plane offset of the own column
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
   const T* const L0 = lds + own;
+  const T* const Q0 = ldq + ((DIM == 3) ? (ty + 1) * QX : 0) + tx + 1;
 
   PlaneMap<T, DIM, PX, PY, NT> pm;
   pm.init(g, x0, y0);
@@ -127,7 +136,8 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     for (int e = (int)threadIdx.x; e < EN; e += NT) {
       const int ex = e % EXN, ey = e / EXN;
       const int q = ((DIM == 3) ? (ey + 1) * PX : 0) + ex + 1;
-      T* b = lds + q;
+      const T* b = lds + q;
+      T* bq = ldq + ey * QX + ex;
       const T* F0 = b + (S_PH + SC) * PLANE;
       const T* Fm = b + (S_PH + SM) * PLANE;
       const T* Fp = b + (S_PH + SP) * PLANE;
@@ -153,9 +163,9 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
           lap += c.w3 * s3;
         }
       }
-      b[(S_MU + SC) * PLANE] = c.a4 * f * (f * f - T(1)) - c.kappa6 * lap;
+      bq[(S_MU + SC) * QPLANE] = c.a4 * f * (f * f - T(1)) - c.kappa6 * lap;
       if (ADV) {
-        b[(S_FX + SC) * PLANE] = f;
+        bq[(S_FX + SC) * QPLANE] = f;
         continue;
       }
       // centre velocity = 1/4 of the sums over its two faces; the factor 1/4
@@ -163,9 +173,9 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
       const T pr = AXI ? f * rnode : f;
       const T* SX = b + S_SX * PLANE;
       const T* SY = b + S_SY * PLANE;
-      b[(S_FX + SC) * PLANE] = pr * (SX[0] + SX[1]);
-      if (DIM == 3) b[(S_FY + SC) * PLANE] = pr * (SY[0] + SY[EY]);
-      b[(S_FZ + SC) * PLANE] = pr * (b[(S_SZ + SC) * PLANE] + b[(S_SZ + SP) * PLANE]);
+      bq[(S_FX + SC) * QPLANE] = pr * (SX[0] + SX[1]);
+      if (DIM == 3) bq[(S_FY + SC) * QPLANE] = pr * (SY[0] + SY[EY]);
+      bq[(S_FZ + SC) * QPLANE] = pr * (b[(S_SZ + SC) * PLANE] + b[(S_SZ + SP) * PLANE]);
     }
   };
 
@@ -190,18 +200,18 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   auto output = [&](int k, auto s0, T phc, T ps, T ac, T ucx, T ucy, T ucz) {
     constexpr int S0 = decltype(s0)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
-    const T* M0 = L0 + (S_MU + S0) * PLANE;
-    const T* Mm = L0 + (S_MU + SM) * PLANE;
-    const T* Mp = L0 + (S_MU + SP) * PLANE;
-    const T* X0 = L0 + (S_FX + S0) * PLANE;
-    const T* Xm = L0 + (S_FX + SM) * PLANE;
-    const T* Xp = L0 + (S_FX + SP) * PLANE;
-    const T* Y0 = L0 + (S_FY + S0) * PLANE;
-    const T* Ym = L0 + (S_FY + SM) * PLANE;
-    const T* Yp = L0 + (S_FY + SP) * PLANE;
-    const T* Z0 = L0 + (S_FZ + S0) * PLANE;
-    const T* Zm = L0 + (S_FZ + SM) * PLANE;
-    const T* Zp = L0 + (S_FZ + SP) * PLANE;
+    const T* M0 = Q0 + (S_MU + S0) * QPLANE;
+    const T* Mm = Q0 + (S_MU + SM) * QPLANE;
+    const T* Mp = Q0 + (S_MU + SP) * QPLANE;
+    const T* X0 = Q0 + (S_FX + S0) * QPLANE;
+    const T* Xm = Q0 + (S_FX + SM) * QPLANE;
+    const T* Xp = Q0 + (S_FX + SP) * QPLANE;
+    const T* Y0 = Q0 + (S_FY + S0) * QPLANE;
+    const T* Ym = Q0 + (S_FY + SM) * QPLANE;
+    const T* Yp = Q0 + (S_FY + SP) * QPLANE;
+    const T* Z0 = Q0 + (S_FZ + S0) * QPLANE;
+    const T* Zm = Q0 + (S_FZ + SM) * QPLANE;
+    const T* Zp = Q0 + (S_FZ + SP) * QPLANE;
     T rp = T(1), rm = T(1), inv_r = T(1);
     if (AXI) {
       const T rk = T(k) + T(0.5);
@@ -227,62 +237,62 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
         flux = ucx * gx + ucz * gz;
       }
     } else {
-      const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + ((M0[EY] - mc) + (M0[-EY] - mc)) +
+      const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + ((M0[QEY] - mc) + (M0[-QEY] - mc)) +
                    ((Mp[0] - mc) + (Mm[0] - mc));
       lap = c.w1 * s1;
       // advective form: isotropic gradient of phi, held in the F_X ring
       T gx = T(0), gy = T(0), gz = T(0);
       if (!ADV) {
-        flux = c.w1 * ((X0[1] - X0[-1]) + (Y0[EY] - Y0[-EY]) + (Zp[0] - Zm[0]));
+        flux = c.w1 * ((X0[1] - X0[-1]) + (Y0[QEY] - Y0[-QEY]) + (Zp[0] - Zm[0]));
       } else {
         gx = c.w1 * (X0[1] - X0[-1]);
-        gy = c.w1 * (X0[EY] - X0[-EY]);
+        gy = c.w1 * (X0[QEY] - X0[-QEY]);
         gz = c.w1 * (Xp[0] - Xm[0]);
       }
       if (c.w2 != T(0)) {
-        const T s2 = ((M0[1 + EY] - mc) + (M0[1 - EY] - mc) + (M0[-1 + EY] - mc) + (M0[-1 - EY] - mc)) +
-                     ((Mp[1] - mc) + (Mp[-1] - mc) + (Mp[EY] - mc) + (Mp[-EY] - mc)) +
-                     ((Mm[1] - mc) + (Mm[-1] - mc) + (Mm[EY] - mc) + (Mm[-EY] - mc));
+        const T s2 = ((M0[1 + QEY] - mc) + (M0[1 - QEY] - mc) + (M0[-1 + QEY] - mc) + (M0[-1 - QEY] - mc)) +
+                     ((Mp[1] - mc) + (Mp[-1] - mc) + (Mp[QEY] - mc) + (Mp[-QEY] - mc)) +
+                     ((Mm[1] - mc) + (Mm[-1] - mc) + (Mm[QEY] - mc) + (Mm[-QEY] - mc));
         lap += c.w2 * s2;
         if (!ADV) {
           // edges: XY in plane k, XZ and YZ in planes k +- 1
-          const T exy = ((X0[1 + EY] + X0[1 - EY]) - (X0[-1 + EY] + X0[-1 - EY])) +
-                        ((Y0[1 + EY] + Y0[-1 + EY]) - (Y0[1 - EY] + Y0[-1 - EY]));
+          const T exy = ((X0[1 + QEY] + X0[1 - QEY]) - (X0[-1 + QEY] + X0[-1 - QEY])) +
+                        ((Y0[1 + QEY] + Y0[-1 + QEY]) - (Y0[1 - QEY] + Y0[-1 - QEY]));
           const T exz = ((Xp[1] - Xp[-1]) + (Xm[1] - Xm[-1])) + ((Zp[1] + Zp[-1]) - (Zm[1] + Zm[-1]));
-          const T eyz = ((Yp[EY] - Yp[-EY]) + (Ym[EY] - Ym[-EY])) + ((Zp[EY] + Zp[-EY]) - (Zm[EY] + Zm[-EY]));
+          const T eyz = ((Yp[QEY] - Yp[-QEY]) + (Ym[QEY] - Ym[-QEY])) + ((Zp[QEY] + Zp[-QEY]) - (Zm[QEY] + Zm[-QEY]));
           flux += c.w2 * (exy + (exz + eyz));
         } else {
           // edge links: XY in plane k, XZ / YZ in planes k +- 1
           const T* P0 = X0;
           const T* Pp = Xp;
           const T* Pm = Xm;
-          gx += c.w2 * (((P0[1 + EY] + P0[1 - EY]) - (P0[-1 + EY] + P0[-1 - EY])) +
+          gx += c.w2 * (((P0[1 + QEY] + P0[1 - QEY]) - (P0[-1 + QEY] + P0[-1 - QEY])) +
                         ((Pp[1] - Pp[-1]) + (Pm[1] - Pm[-1])));
-          gy += c.w2 * (((P0[1 + EY] + P0[-1 + EY]) - (P0[1 - EY] + P0[-1 - EY])) +
-                        ((Pp[EY] - Pp[-EY]) + (Pm[EY] - Pm[-EY])));
-          gz += c.w2 * (((Pp[1] + Pp[-1]) + (Pp[EY] + Pp[-EY])) - ((Pm[1] + Pm[-1]) + (Pm[EY] + Pm[-EY])));
+          gy += c.w2 * (((P0[1 + QEY] + P0[-1 + QEY]) - (P0[1 - QEY] + P0[-1 - QEY])) +
+                        ((Pp[QEY] - Pp[-QEY]) + (Pm[QEY] - Pm[-QEY])));
+          gz += c.w2 * (((Pp[1] + Pp[-1]) + (Pp[QEY] + Pp[-QEY])) - ((Pm[1] + Pm[-1]) + (Pm[QEY] + Pm[-QEY])));
         }
       }
       if (c.w3 != T(0)) {
-        const T s3 = ((Mp[1 + EY] - mc) + (Mp[1 - EY] - mc) + (Mp[-1 + EY] - mc) + (Mp[-1 - EY] - mc)) +
-                     ((Mm[1 + EY] - mc) + (Mm[1 - EY] - mc) + (Mm[-1 + EY] - mc) + (Mm[-1 - EY] - mc));
+        const T s3 = ((Mp[1 + QEY] - mc) + (Mp[1 - QEY] - mc) + (Mp[-1 + QEY] - mc) + (Mp[-1 - QEY] - mc)) +
+                     ((Mm[1 + QEY] - mc) + (Mm[1 - QEY] - mc) + (Mm[-1 + QEY] - mc) + (Mm[-1 - QEY] - mc));
         lap += c.w3 * s3;
         if (!ADV) {
           // corners (sx, sy, sz): sx F_X + sy F_Y + sz F_Z at planes k +- 1
           auto corner = [&](const T* X, const T* Y) {
-            return ((X[1 + EY] + X[1 - EY]) - (X[-1 + EY] + X[-1 - EY])) +
-                   ((Y[1 + EY] + Y[-1 + EY]) - (Y[1 - EY] + Y[-1 - EY]));
+            return ((X[1 + QEY] + X[1 - QEY]) - (X[-1 + QEY] + X[-1 - QEY])) +
+                   ((Y[1 + QEY] + Y[-1 + QEY]) - (Y[1 - QEY] + Y[-1 - QEY]));
           };
-          const T zs = ((Zp[1 + EY] + Zp[1 - EY]) + (Zp[-1 + EY] + Zp[-1 - EY])) -
-                       ((Zm[1 + EY] + Zm[1 - EY]) + (Zm[-1 + EY] + Zm[-1 - EY]));
+          const T zs = ((Zp[1 + QEY] + Zp[1 - QEY]) + (Zp[-1 + QEY] + Zp[-1 - QEY])) -
+                       ((Zm[1 + QEY] + Zm[1 - QEY]) + (Zm[-1 + QEY] + Zm[-1 - QEY]));
           flux += c.w3 * ((corner(Xp, Yp) + corner(Xm, Ym)) + zs);
         } else {
           // corner links (+-1, +-1, +-1) of phi in planes k +- 1
           const T* Pp = Xp;
           const T* Pm = Xm;
-          auto cx = [&](const T* P) { return (P[1 + EY] + P[1 - EY]) - (P[-1 + EY] + P[-1 - EY]); };
-          auto cy = [&](const T* P) { return (P[1 + EY] + P[-1 + EY]) - (P[1 - EY] + P[-1 - EY]); };
-          auto cs = [&](const T* P) { return (P[1 + EY] + P[1 - EY]) + (P[-1 + EY] + P[-1 - EY]); };
+          auto cx = [&](const T* P) { return (P[1 + QEY] + P[1 - QEY]) - (P[-1 + QEY] + P[-1 - QEY]); };
+          auto cy = [&](const T* P) { return (P[1 + QEY] + P[-1 + QEY]) - (P[1 - QEY] + P[-1 - QEY]); };
+          auto cs = [&](const T* P) { return (P[1 + QEY] + P[1 - QEY]) + (P[-1 + QEY] + P[-1 - QEY]); };
           gx += c.w3 * (cx(Pp) + cx(Pm));
           gy += c.w3 * (cy(Pp) + cy(Pm));
           gz += c.w3 * (cs(Pp) - cs(Pm));

@@ -192,7 +192,7 @@ struct ChTile;
 template <typename T>
 struct ChTile<2, T> { static constexpr int TX = 64, TY = 1, BPC = 8; };
 template <>
-struct ChTile<3, float> { static constexpr int TX = 32, TY = 16, BPC = 2; };
+struct ChTile<3, float> { static constexpr int TX = 32, TY = 16, BPC = 3; };
 template <>
 struct ChTile<3, double> { static constexpr int TX = 32, TY = 8, BPC = 2; };
 

@@ -12,14 +12,17 @@ namespace gpe {
 // cell offset with unit signs.  Other tiles map each position through the
 // ghost rules: a cell-centred value, an X-face and a Y-face value get their
 // own offsets, and the X-, Y- and Z-directed velocity components their
-// in-plane signs.  Only the cell offset is kept per load pass; the face
-// offsets and signs of boundary tiles are recomputed when a plane is loaded,
-// which keeps the register footprint of the common interior case small.
+// in-plane signs.  The mapping depends on the in-plane position only, so it
+// is computed once per work-group: per load pass the cell offset and one
+// packed word holding the face offsets relative to it (which stay within a
+// few cells) and the three signs.  A face whose sign is 0 (on a wall or
+// symmetry plane) gets the cell offset, so every address stays in bounds.
 template <typename T, int DIM, int PX, int PY, int NT>
 struct PlaneMap {
   static constexpr int PLANE = PX * PY;
   static constexpr int NPASS = (PLANE + NT - 1) / NT;
   int off_c[NPASS];
+  int pk[NPASS];  // boundary tiles: packed face deltas and signs
   bool ok[NPASS];
   bool interior;
   int x0, y0;
@@ -39,6 +42,12 @@ struct PlaneMap {
     for (int p = 0; p < NPASS; ++p) {
       const Pos q = map(g, p, ok[p]);
       off_c[p] = q.oc;
+      // bits 0-7: X-face delta + 128, 8-15: Y-face delta in rows + 128,
+      // 16-17 / 18-19 / 20-21: sx / sy / sz + 1
+      const int dx = q.sx != T(0) ? q.ox - q.oc : 0;
+      const int dy = q.sy != T(0) ? (q.oy - q.oc) / nx : 0;
+      pk[p] = (dx + 128) | ((dy + 128) << 8) | ((int)q.sx + 1) << 16 | ((int)q.sy + 1) << 18 |
+              ((int)q.sz + 1) << 20;
     }
   }
 
@@ -83,8 +92,10 @@ struct PlaneMap {
   // addressing of load pass p (valid when ok[p])
   __device__ __forceinline__ Pos pos(const Grid& g, int p) const {
     if (interior) return Pos{off_c[p], off_c[p], off_c[p], T(1), T(1), T(1)};
-    bool dummy;
-    return map(g, p, dummy);
+    const int w = pk[p], oc = off_c[p];
+    const int dx = (w & 255) - 128, dy = ((w >> 8) & 255) - 128;
+    return Pos{oc, oc + dx, oc + dy * g.n[0], T(((w >> 16) & 3) - 1), T(((w >> 18) & 3) - 1),
+               T(((w >> 20) & 3) - 1)};
   }
 };
 
