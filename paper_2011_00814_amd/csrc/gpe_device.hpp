@@ -183,7 +183,7 @@ struct FlowTile;
 template <typename T>
 struct FlowTile<2, T> { static constexpr int TX = 64, TY = 1, BPC = 8; };
 template <>
-struct FlowTile<3, float> { static constexpr int TX = 32, TY = 16, BPC = 2; };
+struct FlowTile<3, float> { static constexpr int TX = 32, TY = 8, BPC = 4; };
 template <>
 struct FlowTile<3, double> { static constexpr int TX = 32, TY = 8, BPC = 2; };
 

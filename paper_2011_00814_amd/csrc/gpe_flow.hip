@@ -29,8 +29,10 @@
 
 namespace gpe {
 
-// Occupancy target: 4 waves per SIMD in FP32 (<= 128 VGPRs); the FP64
-// kernel is left to the compiler's register allocation.
+// Occupancy target: 4 waves per SIMD in FP32 (<= 128 VGPRs): four
+// work-groups of 256 threads per CU (32 x 8 tiles, 40 KB of LDS each), so a
+// barrier holds 4 waves and the four groups interleave their phases; the
+// FP64 kernel is left to the compiler's register allocation.
 template <typename T>
 struct FlowOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 1; };
 
