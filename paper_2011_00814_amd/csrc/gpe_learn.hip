@@ -11,9 +11,13 @@
 // FP32.  Weight gradients are an im2col product over
 // chunks of 32 pixels staged in LDS; each work-group writes its partial sums
 // and a second pass adds them in a fixed order, so a training step is
-// bitwise reproducible.
+// bitwise reproducible.  Inference has a fused path (cnn_infer_kernel):
+// network input, all three layers on the matrix cores and the tile sums of
+// the phi output in one persistent kernel with the activations in LDS, then
+// the correction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -485,6 +489,257 @@ __global__ __launch_bounds__(kBlock) void interface_kernel(const float* const* p
   out[q * 2 + 1] = bot;
 }
 
+// ---- fused inference ------------------------------------------------------------------
+// Network input, the three convolutions and the per-tile sums of the phi
+// output for one TW x TH tile of one state per iteration of a persistent
+// work-group, with every activation in LDS: the input on the tile + 3 cells,
+// layer 1 on the tile + 2, layer 2 on the tile + 1, the output on the tile.
+// All three layers run on the matrix cores (the same v_mfma_f32_32x32x8
+// bf16 fragments and K order, tap then 4-channel chunk, as
+// conv_fwd_mfma_kernel; the last layer uses 4 of the 32 output columns).
+// Rows outside [0, H) are zero in every layer's input (zero padding in y);
+// x is periodic.  A region pixel keeps its 32 channels at a 72-byte stride
+// (36 bf16) so that the 32 lanes of a half-wave reading 8 bytes at
+// consecutive pixels spread over the LDS banks.
+constexpr int kTW = 32, kTH = 8;
+constexpr int kR0W = kTW + 6, kR0H = kTH + 6, kR0N = kR0W * kR0H;
+constexpr int kR1W = kTW + 4, kR1H = kTH + 4, kR1N = kR1W * kR1H;
+constexpr int kR2W = kTW + 2, kR2H = kTH + 2, kR2N = kR2W * kR2H;
+constexpr int kAS = 36;  // bf16 slots per pixel of a 32-channel region
+
+__device__ __forceinline__ mfma_bf16x4 unpack4(uint2 v) {
+  mfma_bf16x4 a;
+  a[0] = (short)(v.x & 0xffffu);
+  a[1] = (short)(v.x >> 16);
+  a[2] = (short)(v.y & 0xffffu);
+  a[3] = (short)(v.y >> 16);
+  return a;
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float v) {
+  bf16 b;
+  store(b, v);
+  return b.bits;
+}
+
+__global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const* __restrict__ fields,
+                                                             const float* __restrict__ prm,
+                                                             const bf16* __restrict__ wa, int B, int H, int W,
+                                                             float s0, float s1, float s2, float s3,
+                                                             float* __restrict__ out, float* __restrict__ partial) {
+  __shared__ uint16_t a1[kR1N * kAS];
+  __shared__ uint16_t a2x[kR2N * kAS];  // the input region (4 channels) until layer 1 is done, then layer 2
+  __shared__ uint2 w1s[10 * 32];        // [tap (9 = zero)][output]: 4 input channels
+  __shared__ uint2 w2s[72 * 32];        // [K chunk][output]
+  __shared__ uint2 w3s[72 * 4];
+  __shared__ float bs[68];              // b1, b2, b3
+  __shared__ float red[kBlock / 64];
+  static_assert(kR0N * 4 <= kR2N * kAS, "input region fits the layer-2 buffer");
+
+  // weights and biases once per work-group
+  auto pack = [&](const bf16* src) -> uint2 {
+    uint2 v;
+    v.x = (uint32_t)src[0].bits | ((uint32_t)src[1].bits << 16);
+    v.y = (uint32_t)src[2].bits | ((uint32_t)src[3].bits << 16);
+    return v;
+  };
+  for (int q = threadIdx.x; q < 10 * 32; q += kBlock) {
+    const int tap = q / 32, o = q % 32;
+    w1s[q] = tap < 9 ? pack(wa + OFF_W1 + (size_t)o * 36 + tap * 4) : make_uint2(0u, 0u);
+  }
+  for (int q = threadIdx.x; q < 72 * 32; q += kBlock) w2s[q] = pack(wa + OFF_W2 + (size_t)(q % 32) * 288 + (q / 32) * 4);
+  for (int q = threadIdx.x; q < 72 * 4; q += kBlock) w3s[q] = pack(wa + OFF_W3 + (size_t)(q % 4) * 288 + (q / 4) * 4);
+  for (int q = threadIdx.x; q < 68; q += kBlock)
+    bs[q] = q < 32 ? prm[OFF_B1 + q] : (q < 64 ? prm[OFF_B2 + q - 32] : prm[OFF_B3 + q - 64]);
+
+  const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
+  const int kg = lane / 32, col = lane % 32;
+  const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
+  const int ntiles = B * tiles_x * tiles_y;
+  const float sc[4] = {s0, s1, s2, s3};
+
+  for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
+    const int b = t / (tiles_x * tiles_y);
+    const int tr = t % (tiles_x * tiles_y);
+    const int y0 = (tr / tiles_x) * kTH, x0 = (tr % tiles_x) * kTW;
+    const float* u = fields[4 * b + 0];
+    const float* v = fields[4 * b + 1];
+    const float* p = fields[4 * b + 2];
+    const float* ph = fields[4 * b + 3];
+    __syncthreads();  // weights staged / the previous tile's last layer done with a2x
+
+    // network input on the tile + 3 (as features_kernel)
+    for (int q = threadIdx.x; q < kR0N; q += kBlock) {
+      const int ry = q / kR0W, rx = q % kR0W;
+      const int y = y0 - 3 + ry;
+      const int x = ((x0 - 3 + rx) % W + W) % W;
+      uint2 pk = make_uint2(0u, 0u);
+      if (y >= 0 && y < H) {
+        const size_t o = (size_t)y * W + x;
+        const float uc = 0.5f * (u[o] + u[(size_t)y * W + wrap(x + 1, W)]);
+        const float vn = (y + 1 < H) ? v[o + W] : 0.f;
+        const float vc = 0.5f * (v[o] + vn);
+        pk.x = (uint32_t)bf16_bits(uc / s0) | ((uint32_t)bf16_bits(vc / s1) << 16);
+        pk.y = (uint32_t)bf16_bits(p[o] / s2) | ((uint32_t)bf16_bits(ph[o] / s3) << 16);
+      }
+      *reinterpret_cast<uint2*>(&a2x[q * 4]) = pk;
+    }
+    __syncthreads();
+
+    // Each wave carries two M-tiles (2 w, 2 w + 1, then + 8) with two
+    // independent accumulators, so consecutive MFMAs do not wait on each
+    // other and the B operand is read once for both.
+    // layer 1 on the tile + 2: K = 9 taps x 4 channels, one tap per half-wave
+    for (int m = 2 * wave; m * 32 < kR1N; m += 2 * (kBlock / 64)) {
+      const int d0 = m * 32 + col, d1 = d0 + 32;
+      const bool v0 = d0 < kR1N, v1 = d1 < kR1N;
+      const int ry0 = v0 ? d0 / kR1W : 0, rx0 = v0 ? d0 % kR1W : 0;
+      const int ry1 = v1 ? d1 / kR1W : 0, rx1 = v1 ? d1 % kR1W : 0;
+      mfma_f32x16 acc0, acc1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+#pragma unroll
+      for (int st = 0; st < 5; ++st) {
+        const int tap = 2 * st + kg;
+        mfma_bf16x4 av0 = {0, 0, 0, 0}, av1 = {0, 0, 0, 0};
+        if (tap < 9) {
+          if (v0) av0 = unpack4(*reinterpret_cast<const uint2*>(&a2x[((ry0 + tap / 3) * kR0W + rx0 + tap % 3) * 4]));
+          if (v1) av1 = unpack4(*reinterpret_cast<const uint2*>(&a2x[((ry1 + tap / 3) * kR0W + rx1 + tap % 3) * 4]));
+        }
+        const mfma_bf16x4 bv = unpack4(w1s[tap * 32 + col]);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av0, bv, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av1, bv, acc1, 0, 0, 0);
+      }
+      const float bo = bs[col];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int dd = (m + h) * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
+          if (dd < kR1N) {
+            const int y = y0 - 2 + dd / kR1W;
+            const float a = h ? acc1[r] : acc0[r];
+            a1[dd * kAS + col] = (y >= 0 && y < H) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // layers 2 and 3 share the 32-channel implicit GEMM on two M-tiles:
+    // destination pixel (ry, rx) of a region reads the source region of
+    // width SW (two cells wider) at (ry + dy + 1, rx + dx + 1)
+    auto conv32x2 = [&](const uint16_t* src, int SW, int ry0, int rx0, bool v0, int ry1, int rx1, bool v1,
+                        const uint2* wt, bool cols4, mfma_f32x16& acc0, mfma_f32x16& acc1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+#pragma unroll 1
+      for (int tap = 0; tap < 9; ++tap) {
+        const uint16_t* sp0 = src + ((ry0 + tap / 3) * SW + rx0 + tap % 3) * kAS;
+        const uint16_t* sp1 = src + ((ry1 + tap / 3) * SW + rx1 + tap % 3) * kAS;
+#pragma unroll
+        for (int c = 0; c < 32; c += 8) {
+          const int c0 = c + 4 * kg;
+          mfma_bf16x4 av0 = {0, 0, 0, 0}, av1 = {0, 0, 0, 0};
+          if (v0) av0 = unpack4(*reinterpret_cast<const uint2*>(sp0 + c0));
+          if (v1) av1 = unpack4(*reinterpret_cast<const uint2*>(sp1 + c0));
+          const int kc = (tap * 32 + c0) / 4;
+          mfma_bf16x4 bv = {0, 0, 0, 0};
+          if (!cols4)
+            bv = unpack4(wt[kc * 32 + col]);
+          else if (col < 4)
+            bv = unpack4(wt[kc * 4 + col]);
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av0, bv, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av1, bv, acc1, 0, 0, 0);
+        }
+      }
+    };
+
+    // layer 2 on the tile + 1
+    for (int m = 2 * wave; m * 32 < kR2N; m += 2 * (kBlock / 64)) {
+      const int d0 = m * 32 + col, d1 = d0 + 32;
+      const bool v0 = d0 < kR2N, v1 = d1 < kR2N;
+      mfma_f32x16 acc0, acc1;
+      conv32x2(a1, kR1W, v0 ? d0 / kR2W : 0, v0 ? d0 % kR2W : 0, v0, v1 ? d1 / kR2W : 0, v1 ? d1 % kR2W : 0, v1,
+               w2s, false, acc0, acc1);
+      const float bo = bs[32 + col];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int dd = (m + h) * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
+          if (dd < kR2N) {
+            const int y = y0 - 1 + dd / kR2W;
+            const float a = h ? acc1[r] : acc0[r];
+            a2x[dd * kAS + col] = (y >= 0 && y < H) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // layer 3 on the tile: M-tile m is tile row m (32 columns), rows 2 w and
+    // 2 w + 1 per wave; lanes with output column < 4 write the result and
+    // the phi column's tile sum
+    float psum = 0.f;
+    {
+      static_assert(kTH == 2 * (kBlock / 64), "two tile rows per wave");
+      const int m = 2 * wave;
+      mfma_f32x16 acc0, acc1;
+      conv32x2(a2x, kR2W, m, col, true, m + 1, col, true, w3s, true, acc0, acc1);
+      if (col < 4) {
+        const float bo = bs[64 + col];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int y = y0 + m + h;
+          if (y >= H) continue;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int xc = x0 + 8 * (r / 4) + 4 * kg + (r % 4);
+            if (xc < W) {
+              const float val = (h ? acc1[r] : acc0[r]) + bo;
+              out[(((size_t)b * H + y) * W + xc) * 4 + col] = val;
+              if (col == 3) psum += val;
+            }
+          }
+        }
+      }
+    }
+    // tile sum of the phi output: lanes 3 and 35 of each wave, then the waves
+    psum += __shfl_xor(psum, 32, 64);
+    if (lane == 3) red[wave] = psum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float s = 0.f;
+      for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+      partial[t] = s;
+    }
+  }
+  (void)sc;
+}
+
+// correction with the case mean of the phi output from the per-tile sums
+__global__ __launch_bounds__(kBlock) void apply_tiles_kernel(float* const* fields, const float* out, int B, int H,
+                                                             int W, float s0, float s1, float s2, float s3,
+                                                             const float* partial, int tiles_per_case) {
+  const long n = (long)B * H * W;
+  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int x = (int)(q % W);
+  const long r = q / W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  float sum = 0.f;
+  for (int t = 0; t < tiles_per_case; ++t) sum += partial[(size_t)b * tiles_per_case + t];
+  const size_t o = (size_t)y * W + x;
+  const float* d = out + q * 4;
+  const float mean = sum / (float)(H * W);
+  fields[4 * b + 0][o] += s0 * d[0];
+  if (y > 0) fields[4 * b + 1][o] += s1 * d[1];
+  fields[4 * b + 2][o] += s2 * d[2];
+  fields[4 * b + 3][o] += s3 * (d[3] - mean);
+}
+
 // ---- launch helpers ----------------------------------------------------------------
 bool dims_ok(int B, int H, int W) { return B >= 1 && H >= 1 && W >= 1 && (long)B * H * W < (1L << 31); }
 
@@ -679,6 +934,40 @@ int gpe_cnn_apply(float* const* d_fields, const float* d_out, int32_t B, int32_t
   hipLaunchKernelGGL(phi_sum_kernel, dim3(B), dim3(kBlock), 0, s, d_out, H * W, d_scratch);
   hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
                      out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)d_scratch);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+size_t gpe_cnn_infer_scratch_bytes(int32_t B, int32_t H, int32_t W) {
+  if (!dims_ok(B, H, W)) return 0;
+  return (size_t)B * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH) * sizeof(float);
+}
+
+int gpe_cnn_infer(float* const* d_fields, const float* d_params, const void* d_params_bf16, int32_t B, int32_t H,
+                  int32_t W, const float in_scale[4], const float out_scale[4], float* d_out, void* d_scratch,
+                  size_t scratch_bytes, void* stream) {
+  if (!d_fields || !d_params || !d_params_bf16 || !in_scale || !out_scale || !d_out || !d_scratch ||
+      !dims_ok(B, H, W))
+    return GPE_EINVAL;
+  for (int c = 0; c < 4; ++c)
+    if (!(in_scale[c] > 0.f)) return GPE_EINVAL;
+  if (scratch_bytes < gpe_cnn_infer_scratch_bytes(B, H, W)) return GPE_EINVAL;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int tpc = ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
+  const long ntiles = (long)B * tpc;
+  const unsigned grid = (unsigned)std::min<long>(ntiles, 2L * ncu);
+  float* partial = (float*)d_scratch;
+  hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(kBlock), 0, s, d_fields, d_params,
+                     (const bf16*)d_params_bf16, B, H, W, in_scale[0], in_scale[1], in_scale[2], in_scale[3], d_out,
+                     partial);
+  hipLaunchKernelGGL(apply_tiles_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B,
+                     H, W, out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)partial, tpc);
   return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
 }
 

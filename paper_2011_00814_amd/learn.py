@@ -45,6 +45,8 @@ def lib():
             "gpe_cnn_adam": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i64, vp], ctypes.c_int),
             "gpe_cnn_apply": ([vp, vp, i32, i32, i32, f4, vp, vp], ctypes.c_int),
             "gpe_interface_position": ([vp, i32, i32, i32, vp, vp], ctypes.c_int),
+            "gpe_cnn_infer_scratch_bytes": ([i32, i32, i32], sz),
+            "gpe_cnn_infer": ([vp, vp, vp, i32, i32, i32, f4, f4, vp, vp, sz, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -123,6 +125,15 @@ def gpe_cnn_apply(table, out, B, H, W, out_scale, scratch, stream):
            "gpe_cnn_apply")
 
 
+def gpe_cnn_infer_scratch_bytes(B: int, H: int, W: int) -> int:
+    return int(lib().gpe_cnn_infer_scratch_bytes(B, H, W))
+
+
+def gpe_cnn_infer(table, params, params_bf16, B, H, W, in_scale, out_scale, out, scratch, scratch_bytes, stream):
+    _check(lib().gpe_cnn_infer(_vp(table), _vp(params), _vp(params_bf16), B, H, W, _f4(in_scale), _f4(out_scale),
+                               _vp(out), _vp(scratch), scratch_bytes, _vp(stream)), "gpe_cnn_infer")
+
+
 def gpe_interface_position(table, B, H, W, out, stream):
     _check(lib().gpe_interface_position(_vp(table), B, H, W, _vp(out), _vp(stream)), "gpe_interface_position")
 
@@ -187,6 +198,8 @@ class CNN:
         self.loss_buf = torch.zeros(1, **f32)
         self.scratch_bytes = gpe_cnn_scratch_bytes(B, H, W)
         self.scratch = torch.zeros(self.scratch_bytes // 4 + 1, **f32)
+        self.infer_bytes = gpe_cnn_infer_scratch_bytes(B, H, W)
+        self.infer_scratch = torch.zeros(self.infer_bytes // 4 + 1, **f32)
         self.step_count = 0
         self.convert()
 
@@ -221,6 +234,15 @@ class CNN:
 
     def apply(self, table, B, out_scale):
         gpe_cnn_apply(table.data_ptr(), self.out.data_ptr(), B, self.H, self.W, out_scale, self.scratch.data_ptr(),
+                      self.sid)
+
+    def infer(self, table, B, in_scale, out_scale):
+        """Network input, forward pass and correction of B states in the
+        fused BF16 kernel (the output also lands in self.out)."""
+        if self.act_type != GPE_ACT_BF16:
+            raise ValueError("the fused inference path uses BF16 operands")
+        gpe_cnn_infer(table.data_ptr(), self.params.data_ptr(), self.params_act.data_ptr(), B, self.H, self.W,
+                      in_scale, out_scale, self.out.data_ptr(), self.infer_scratch.data_ptr(), self.infer_bytes,
                       self.sid)
 
     def synchronize(self):

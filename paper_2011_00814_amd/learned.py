@@ -235,7 +235,7 @@ def one_step_gain(net, data, in_scale, out_scale, device="cuda:0", batch=None):
 
 
 def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1024, device="cuda:0",
-             log=print, graph_steps=10, checkpoints=4, autotune=True):
+             log=print, graph_steps=10, checkpoints=4, autotune=True, fused=True):
     """Fine runs of `seeds` against coarse runs from their restricted
     initial states, without and with the network (one correction per
     coarse step), fine_steps / factor coarse steps, compared at
@@ -277,11 +277,16 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
     torch.cuda.synchronize()
     rtab = _table(rstore.ptrs(range(B)), device)
 
+    fused = fused and net.act_type == Lr.GPE_ACT_BF16
+
     def corrected_step():
         ens_n.run(1)  # one batch step, launched (not replayed) so that it can be captured
-        cnet.features(ntab, B, in_scale)
-        cnet.forward(B)
-        cnet.apply(ntab, B, out_scale)
+        if fused:  # network input, forward pass and correction in two launches
+            cnet.infer(ntab, B, in_scale, out_scale)
+        else:
+            cnet.features(ntab, B, in_scale)
+            cnet.forward(B)
+            cnet.apply(ntab, B, out_scale)
 
     # graph_steps corrected steps captured as one HIP graph on the coarse
     # stream (every launch goes to that stream; nothing allocates);
@@ -353,7 +358,7 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
         "grid_fine": [nx, ny], "grid_coarse": [Wc, H], "error_unit": f"coarse cells ({factor} fine cells)",
         "fine_ms": round(fine_ms, 2), "coarse_ms": round(coarse_ms, 2), "coarse_net_ms": round(net_ms, 2),
         "speedup_vs_fine": round(fine_ms / net_ms, 2), "speedup_plain_coarse": round(fine_ms / coarse_ms, 2),
-        "fine_finite": int(ens_f.finite().sum()),
+        "inference": "fused" if fused else "unfused", "fine_finite": int(ens_f.finite().sum()),
         "plain_coarse": last["plain_coarse"], "learned_coarse": dict(last["learned_coarse"],
                                                                       fallback_to_fine=int((flags_n == 0).sum())),
         "checkpoints": series,

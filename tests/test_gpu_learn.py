@@ -132,6 +132,47 @@ def test_forward_and_backward_match_oracle(L, act):
         assert ew < tol_g and eb < tol_g, (layer, ew, eb)
 
 
+@pytest.mark.parametrize("B,H,W", [(3, 16, 64), (2, 20, 50), (1, 64, 256)])
+def test_fused_inference_matches_unfused_path_and_oracle(L, B, H, W):
+    """gpe_cnn_infer (network input, three layers on the matrix cores with the
+    activations in LDS, correction) against gpe_cnn_features + forward +
+    apply with BF16 operands, and its output against the CPU reference fed
+    the same BF16 operands; ragged tiles in x and y included."""
+    import torch
+
+    params = _params(21)
+    states = _random_states(B, H, W, 22)
+    out_scale = (1e-3, 2e-3, 1e-4, 0.01)
+    ta, taba = _upload(states)
+    tb, tabb = _upload(states)
+    net = L.CNN(B, H, W, act_type=L.GPE_ACT_BF16, params=L.pack_params(params))
+    _say(f"[learn] fused inference B={B} H={H} W={W}")
+    net.features(taba, B, SCALE_IN)
+    net.forward(B)
+    net.apply(taba, B, out_scale)
+    net.synchronize()
+    ref_out = net.out.cpu().numpy().reshape(B, H, W, 4).copy()
+    x0 = L.bf16_to_float(net.x0).astype(np.float64).reshape(B, H, W, 4)
+    net.out.zero_()
+    net.infer(tabb, B, SCALE_IN, out_scale)
+    net.synchronize()
+    got = net.out.cpu().numpy().reshape(B, H, W, 4)
+    # layers 1 and 2 are the same instructions in the same order; the last
+    # layer and the phi sum add in another order
+    assert _rel(got, ref_out) < 1e-5, _rel(got, ref_out)
+    for q in range(4 * B):
+        a, b = ta[q].cpu().numpy(), tb[q].cpu().numpy()
+        assert np.max(np.abs(a - b)) <= 1e-6 * max(1e-3, np.max(np.abs(a))), q
+    wa = L.bf16_to_float(net.params_act).astype(np.float64)
+    master = L.pack_params(params).astype(np.float32).astype(np.float64)
+    p_ref = [(w, bb) for (w, _), (_, bb) in zip(L.unpack_params(wa), L.unpack_params(master))]
+    out, _ = C.forward(p_ref, x0)  # FP64 activations: the kernels round them to BF16
+    assert _rel(got, out) < 2e-2
+    # the phase mass of every state is kept
+    for b in range(B):
+        assert abs(tb[4 * b + 3].cpu().numpy().astype(np.float64).sum() - states[b]["phi"].sum()) < 1e-3
+
+
 def test_adam_matches_update_rule(L):
     import torch
 

@@ -29,6 +29,16 @@ def test_exports_every_header_symbol(G):
         assert hasattr(L, n), n
 
 
+def test_exports_every_learn_header_symbol(G):
+    from paper_2011_00814_amd import learn
+
+    names = learn.header_functions()
+    assert len(names) == 15
+    L = G.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
 def test_struct_sizes_match_header_layout(G):
     # 8-byte aligned layouts with no implicit padding
     assert ctypes.sizeof(G.gpe_params) == 4 * 14 + 8 * 13 + 4 * 2 + 8 * 6
