@@ -188,6 +188,8 @@ __global__ __launch_bounds__(kBlock) void conv_fwd_kernel(const TA* __restrict__
 // taps with the last zero); CI a multiple of 8 keeps a K-step inside one tap.
 typedef short mfma_bf16x4 __attribute__((ext_vector_type(4)));
 typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int mfma_u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mfma_bf16x8 __attribute__((ext_vector_type(8)));
 
 template <int CI, bool RELU>
 __global__ __launch_bounds__(kBlock) void conv_fwd_mfma_kernel(const bf16* __restrict__ x, const bf16* __restrict__ w,
@@ -494,9 +496,9 @@ __global__ __launch_bounds__(kBlock) void interface_kernel(const float* const* p
 // output for one TW x TH tile of one state per iteration of a persistent
 // work-group, with every activation in LDS: the input on the tile + 3 cells,
 // layer 1 on the tile + 2, layer 2 on the tile + 1, the output on the tile.
-// All three layers run on the matrix cores (the same v_mfma_f32_32x32x8
-// bf16 fragments and K order, tap then 4-channel chunk, as
-// conv_fwd_mfma_kernel; the last layer uses 4 of the 32 output columns).
+// All three layers run on the matrix cores with the double-K instruction
+// v_mfma_f32_32x32x16_bf16 in the K order tap, then channel (the last
+// layer uses 4 of the 32 output columns).
 // Rows outside [0, H) are zero in every layer's input (zero padding in y);
 // x is periodic.  A region pixel keeps its 32 channels at a 72-byte stride
 // (36 bf16) so that the 32 lanes of a half-wave reading 8 bytes at
@@ -516,11 +518,9 @@ __device__ __forceinline__ mfma_bf16x4 unpack4(uint2 v) {
   return a;
 }
 
-__device__ __forceinline__ uint16_t bf16_bits(float v) {
-  bf16 b;
-  store(b, v);
-  return b.bits;
-}
+// round to nearest even in one instruction (v_cvt_pk_bf16_f32); equal to
+// store(bf16&, float) except for the payload of a NaN
+__device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
 __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const* __restrict__ fields,
                                                              const float* __restrict__ prm,
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
                                                              float* __restrict__ out, float* __restrict__ partial) {
   __shared__ uint16_t a1[kR1N * kAS];
   __shared__ uint16_t a2x[kR2N * kAS];  // the input region (4 channels) until layer 1 is done, then layer 2
-  __shared__ uint2 w1s[10 * 32];        // [tap (9 = zero)][output]: 4 input channels
+  __shared__ uint2 w1s[12 * 32];        // [tap (9-11 zero)][output]: 4 input channels
   __shared__ uint2 w2s[72 * 32];        // [K chunk][output]
   __shared__ uint2 w3s[72 * 4];
   __shared__ float bs[68];              // b1, b2, b3
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
     v.y = (uint32_t)src[2].bits | ((uint32_t)src[3].bits << 16);
     return v;
   };
-  for (int q = threadIdx.x; q < 10 * 32; q += kBlock) {
+  for (int q = threadIdx.x; q < 12 * 32; q += kBlock) {
     const int tap = q / 32, o = q % 32;
     w1s[q] = tap < 9 ? pack(wa + OFF_W1 + (size_t)o * 36 + tap * 4) : make_uint2(0u, 0u);
   }
@@ -588,8 +588,22 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
 
     // Each wave carries two M-tiles (2 w, 2 w + 1, then + 8) with two
     // independent accumulators, so consecutive MFMAs do not wait on each
-    // other and the B operand is read once for both.
-    // layer 1 on the tile + 2: K = 9 taps x 4 channels, one tap per half-wave
+    // other and the B operand is read once for both.  The double-K
+    // instruction v_mfma_f32_32x32x16_bf16 takes 8 consecutive K values per
+    // lane: lane l holds A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t][l % 32]
+    // (t < 8); D is laid out as for v_mfma_f32_32x32x8.
+    // (two packed bf16 per 32-bit word, element 0 in the low half: the
+    // words are the operand as they are)
+    auto mfma16 = [&](uint2 a_lo, uint2 a_hi, uint2 b_lo, uint2 b_hi, mfma_f32x16 acc) {
+      const mfma_u32x4 av = {a_lo.x, a_lo.y, a_hi.x, a_hi.y};
+      const mfma_u32x4 bv = {b_lo.x, b_lo.y, b_hi.x, b_hi.y};
+      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(mfma_bf16x8, av),
+                                                      __builtin_bit_cast(mfma_bf16x8, bv), acc, 0, 0, 0);
+    };
+    const uint2 z2 = make_uint2(0u, 0u);
+
+    // layer 1 on the tile + 2: K = 9 taps x 4 channels; a K-step of 16
+    // holds taps 4 s + 2 kg and 4 s + 2 kg + 1 in a half-wave (taps 9-11 zero)
     for (int m = 2 * wave; m * 32 < kR1N; m += 2 * (kBlock / 64)) {
       const int d0 = m * 32 + col, d1 = d0 + 32;
       const bool v0 = d0 < kR1N, v1 = d1 < kR1N;
@@ -599,58 +613,61 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
 #pragma unroll
-      for (int st = 0; st < 5; ++st) {
-        const int tap = 2 * st + kg;
-        mfma_bf16x4 av0 = {0, 0, 0, 0}, av1 = {0, 0, 0, 0};
-        if (tap < 9) {
-          if (v0) av0 = unpack4(*reinterpret_cast<const uint2*>(&a2x[((ry0 + tap / 3) * kR0W + rx0 + tap % 3) * 4]));
-          if (v1) av1 = unpack4(*reinterpret_cast<const uint2*>(&a2x[((ry1 + tap / 3) * kR0W + rx1 + tap % 3) * 4]));
-        }
-        const mfma_bf16x4 bv = unpack4(w1s[tap * 32 + col]);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av0, bv, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av1, bv, acc1, 0, 0, 0);
+      for (int st = 0; st < 3; ++st) {
+        const int ta = 4 * st + 2 * kg, tb = ta + 1;
+        auto xin = [&](int ry, int rx, int tap) -> uint2 {
+          return tap < 9 ? *reinterpret_cast<const uint2*>(&a2x[((ry + tap / 3) * kR0W + rx + tap % 3) * 4]) : z2;
+        };
+        const uint2 wa_ = w1s[ta * 32 + col], wb_ = w1s[tb * 32 + col];
+        acc0 = mfma16(xin(ry0, rx0, ta), xin(ry0, rx0, tb), wa_, wb_, acc0);
+        acc1 = mfma16(xin(ry1, rx1, ta), xin(ry1, rx1, tb), wa_, wb_, acc1);
       }
       const float bo = bs[col];
+      // region rows inside the image: dd in [in_lo, in_hi)
+      const int in_lo = max(0, 2 - y0) * kR1W, in_hi = min(kR1H, H - y0 + 2) * kR1W;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int dd = (m + h) * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
           if (dd < kR1N) {
-            const int y = y0 - 2 + dd / kR1W;
             const float a = h ? acc1[r] : acc0[r];
-            a1[dd * kAS + col] = (y >= 0 && y < H) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
+            a1[dd * kAS + col] = (dd >= in_lo && dd < in_hi) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
           }
         }
       }
     }
     __syncthreads();
 
-    // layers 2 and 3 share the 32-channel implicit GEMM on two M-tiles:
-    // destination pixel (ry, rx) of a region reads the source region of
-    // width SW (two cells wider) at (ry + dy + 1, rx + dx + 1)
-    auto conv32x2 = [&](const uint16_t* src, int SW, int ry0, int rx0, bool v0, int ry1, int rx1, bool v1,
-                        const uint2* wt, bool cols4, mfma_f32x16& acc0, mfma_f32x16& acc1) {
+    // layers 2 and 3: the 32-channel implicit GEMM on two M-tiles; the
+    // destination pixel (ry, rx) reads the source region of width SW (two
+    // cells wider) at (ry + dy + 1, rx + dx + 1); a K-step of 16 is one tap
+    // and 16 channels, 8 per half-wave (two 8-byte LDS reads).  Rows of
+    // invalid pixels read pixel (0, 0) of the region and are never stored.
+    auto conv32x2 = [&](const uint16_t* src, int SW, int ry0, int rx0, int ry1, int rx1, const uint2* wt,
+                        bool cols4, mfma_f32x16& acc0, mfma_f32x16& acc1) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
-#pragma unroll 1
+#pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const uint16_t* sp0 = src + ((ry0 + tap / 3) * SW + rx0 + tap % 3) * kAS;
         const uint16_t* sp1 = src + ((ry1 + tap / 3) * SW + rx1 + tap % 3) * kAS;
 #pragma unroll
-        for (int c = 0; c < 32; c += 8) {
-          const int c0 = c + 4 * kg;
-          mfma_bf16x4 av0 = {0, 0, 0, 0}, av1 = {0, 0, 0, 0};
-          if (v0) av0 = unpack4(*reinterpret_cast<const uint2*>(sp0 + c0));
-          if (v1) av1 = unpack4(*reinterpret_cast<const uint2*>(sp1 + c0));
-          const int kc = (tap * 32 + c0) / 4;
-          mfma_bf16x4 bv = {0, 0, 0, 0};
-          if (!cols4)
-            bv = unpack4(wt[kc * 32 + col]);
-          else if (col < 4)
-            bv = unpack4(wt[kc * 4 + col]);
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av0, bv, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av1, bv, acc1, 0, 0, 0);
+        for (int c = 0; c < 32; c += 16) {
+          const int c0 = c + 8 * kg;
+          const int kc = (tap * 32 + c0) / 4;  // first 4-value chunk of the lane's 8 K values
+          uint2 b_lo = z2, b_hi = z2;
+          if (!cols4) {
+            b_lo = wt[kc * 32 + col];
+            b_hi = wt[(kc + 1) * 32 + col];
+          } else if (col < 4) {
+            b_lo = wt[kc * 4 + col];
+            b_hi = wt[(kc + 1) * 4 + col];
+          }
+          acc0 = mfma16(*reinterpret_cast<const uint2*>(sp0 + c0), *reinterpret_cast<const uint2*>(sp0 + c0 + 4),
+                        b_lo, b_hi, acc0);
+          acc1 = mfma16(*reinterpret_cast<const uint2*>(sp1 + c0), *reinterpret_cast<const uint2*>(sp1 + c0 + 4),
+                        b_lo, b_hi, acc1);
         }
       }
     };
@@ -660,18 +677,18 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
       const int d0 = m * 32 + col, d1 = d0 + 32;
       const bool v0 = d0 < kR2N, v1 = d1 < kR2N;
       mfma_f32x16 acc0, acc1;
-      conv32x2(a1, kR1W, v0 ? d0 / kR2W : 0, v0 ? d0 % kR2W : 0, v0, v1 ? d1 / kR2W : 0, v1 ? d1 % kR2W : 0, v1,
-               w2s, false, acc0, acc1);
+      conv32x2(a1, kR1W, v0 ? d0 / kR2W : 0, v0 ? d0 % kR2W : 0, v1 ? d1 / kR2W : 0, v1 ? d1 % kR2W : 0, w2s,
+               false, acc0, acc1);
       const float bo = bs[32 + col];
+      const int in_lo = max(0, 1 - y0) * kR2W, in_hi = min(kR2H, H - y0 + 1) * kR2W;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int dd = (m + h) * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
           if (dd < kR2N) {
-            const int y = y0 - 1 + dd / kR2W;
             const float a = h ? acc1[r] : acc0[r];
-            a2x[dd * kAS + col] = (y >= 0 && y < H) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
+            a2x[dd * kAS + col] = (dd >= in_lo && dd < in_hi) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
           }
         }
       }
@@ -686,7 +703,7 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
       static_assert(kTH == 2 * (kBlock / 64), "two tile rows per wave");
       const int m = 2 * wave;
       mfma_f32x16 acc0, acc1;
-      conv32x2(a2x, kR2W, m, col, true, m + 1, col, true, w3s, true, acc0, acc1);
+      conv32x2(a2x, kR2W, m, col, m + 1, col, w3s, true, acc0, acc1);
       if (col < 4) {
         const float bo = bs[64 + col];
 #pragma unroll
@@ -718,26 +735,14 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
   (void)sc;
 }
 
-// correction with the case mean of the phi output from the per-tile sums
-__global__ __launch_bounds__(kBlock) void apply_tiles_kernel(float* const* fields, const float* out, int B, int H,
-                                                             int W, float s0, float s1, float s2, float s3,
-                                                             const float* partial, int tiles_per_case) {
-  const long n = (long)B * H * W;
-  const long q = (long)blockIdx.x * kBlock + threadIdx.x;
-  if (q >= n) return;
-  const int x = (int)(q % W);
-  const long r = q / W;
-  const int y = (int)(r % H);
-  const int b = (int)(r / H);
-  float sum = 0.f;
-  for (int t = 0; t < tiles_per_case; ++t) sum += partial[(size_t)b * tiles_per_case + t];
-  const size_t o = (size_t)y * W + x;
-  const float* d = out + q * 4;
-  const float mean = sum / (float)(H * W);
-  fields[4 * b + 0][o] += s0 * d[0];
-  if (y > 0) fields[4 * b + 1][o] += s1 * d[1];
-  fields[4 * b + 2][o] += s2 * d[2];
-  fields[4 * b + 3][o] += s3 * (d[3] - mean);
+// per-case sums of the phi output from the per-tile sums, in tile order
+__global__ __launch_bounds__(kBlock) void case_sums_kernel(const float* partial, int B, int tiles_per_case,
+                                                           float* sums) {
+  const int b = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (b >= B) return;
+  float s = 0.f;
+  for (int t = 0; t < tiles_per_case; ++t) s += partial[(size_t)b * tiles_per_case + t];
+  sums[b] = s;
 }
 
 // ---- launch helpers ----------------------------------------------------------------
@@ -939,7 +944,7 @@ int gpe_cnn_apply(float* const* d_fields, const float* d_out, int32_t B, int32_t
 
 size_t gpe_cnn_infer_scratch_bytes(int32_t B, int32_t H, int32_t W) {
   if (!dims_ok(B, H, W)) return 0;
-  return (size_t)B * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH) * sizeof(float);
+  return ((size_t)B * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH) + B) * sizeof(float);
 }
 
 int gpe_cnn_infer(float* const* d_fields, const float* d_params, const void* d_params_bf16, int32_t B, int32_t H,
@@ -966,8 +971,10 @@ int gpe_cnn_infer(float* const* d_fields, const float* d_params, const void* d_p
   hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(kBlock), 0, s, d_fields, d_params,
                      (const bf16*)d_params_bf16, B, H, W, in_scale[0], in_scale[1], in_scale[2], in_scale[3], d_out,
                      partial);
-  hipLaunchKernelGGL(apply_tiles_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B,
-                     H, W, out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)partial, tpc);
+  float* sums = partial + ntiles;
+  hipLaunchKernelGGL(case_sums_kernel, dim3(blocks_for(B)), dim3(kBlock), 0, s, (const float*)partial, B, tpc, sums);
+  hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
+                     out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)sums);
   return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
 }
 
