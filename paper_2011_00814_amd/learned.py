@@ -310,8 +310,11 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
     def run_net():
         done = 0
         if graph is not None:
-            for _ in range(seg_c // graph_steps):
-                graph.replay()
+            # a graph replays on torch's current stream: make that the coarse
+            # stream, on which the timing events and the next reads are
+            with torch.cuda.stream(ens_c.stream):
+                for _ in range(seg_c // graph_steps):
+                    graph.replay()
             done = (seg_c // graph_steps) * graph_steps
         for _ in range(seg_c - done):
             corrected_step()
