@@ -14,6 +14,7 @@ import math
 import numpy as np
 import pytest
 
+from oracle.oracle import FLOW_RK2, NO_BULK, NO_PAVG
 from paper_2011_00814_amd import workloads as W
 
 
@@ -225,6 +226,62 @@ def test_acoustic_mode_exact(oracle, dim, modes):
         st[keys[a]] = field(q0[1 + a], a)
     out = oracle.run(prob, st, nsteps)
     scale = np.max(np.abs(qn))
+    assert np.max(np.abs(out["p"] - field(qn[0], -1))) <= 1e-5 * scale
+    for a in range(dim):
+        assert np.max(np.abs(out[keys[a]] - field(qn[1 + a], a))) <= 1e-5 * scale
+
+
+def mat_R2(A):
+    I = np.eye(A.shape[0], dtype=A.dtype)
+    return I + A + A @ A / 2
+
+
+# The ablation switches of the oracle against the same per-mode symbols with
+# the corresponding factor removed: pressure gradient without the transverse
+# average and bulk viscosity set to zero (Sec. 4, drop coalescence in 3-D),
+# TVD-RK2 in place of TVD-RK3 for the flow (Sec. 3).  The mode has a
+# transverse wavenumber, so the average matters, and is compressional, so
+# the bulk term matters.
+@pytest.mark.parametrize("flags", [NO_PAVG, NO_BULK, NO_PAVG | NO_BULK, FLOW_RK2])
+@pytest.mark.parametrize("dim,modes", [(2, (2, 3, 0)), (3, (2, 1, 3))])
+def test_acoustic_mode_ablation_switches(oracle, dim, modes, flags):
+    n = (16, 12, 8) if dim == 3 else (16, 12, 1)
+    phi0 = 0.4
+    prob = W.base_problem(dim=dim, n=n, rho_l=1.0, rho_g=0.5, eta_l=0.05, eta_g=0.02,
+                          mob=0.0, dt=0.8, cs2=0.3)
+    prob["flags"] = flags
+    rho = 0.5 * (1.0 * (1 + phi0) + 0.5 * (1 - phi0))
+    eta = 0.5 * (0.05 * (1 + phi0) + 0.02 * (1 - phi0))
+    k = [2 * math.pi * modes[a] / n[a] if a < dim else 0.0 for a in range(3)]
+    A = acoustic_matrix(k[:dim], rho, eta, prob["cs2"], dim,
+                        pavg=not flags & NO_PAVG, bulk=not flags & NO_BULK)
+    A_paper = acoustic_matrix(k[:dim], rho, eta, prob["cs2"], dim)
+    R = mat_R2 if flags & FLOW_RK2 else mat_R3
+    eps = 1e-7
+    q0 = np.array([1.0] + [0.3 - 0.2j * a for a in range(dim)], dtype=complex) * eps
+    nsteps = 25
+    qn = np.linalg.matrix_power(R(prob["dt"] * A), nsteps) @ q0
+    q_paper = np.linalg.matrix_power(mat_R3(prob["dt"] * A_paper), nsteps) @ q0
+    nx, ny, nz = n
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pos_c = [xx + 0.5, yy + 0.5, zz + 0.5]
+
+    def field(amp, shift_axis):
+        pos = [pos_c[a] - (0.5 if a == shift_axis else 0.0) for a in range(3)]
+        ph = sum(k[a] * pos[a] for a in range(dim))
+        return np.real(amp * np.exp(1j * ph))
+
+    st = W.zero_state(prob)
+    st["phi"][:] = phi0
+    st["p"] = field(q0[0], -1)
+    keys = "uvw"
+    for a in range(dim):
+        st[keys[a]] = field(q0[1 + a], a)
+    out = oracle.run(prob, st, nsteps)
+    scale = np.max(np.abs(qn))
+    # the switched scheme is a different one: its closed form differs from the
+    # paper scheme's by far more than the tolerance
+    assert np.max(np.abs(qn - q_paper)) > 1e-3 * scale
     assert np.max(np.abs(out["p"] - field(qn[0], -1))) <= 1e-5 * scale
     for a in range(dim):
         assert np.max(np.abs(out[keys[a]] - field(qn[1 + a], a))) <= 1e-5 * scale
