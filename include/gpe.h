@@ -82,6 +82,19 @@ enum gpe_init_kind {
  * The batched ensemble (gpe_ensemble_*) supports the conservative form only. */
 enum gpe_ch_transport { GPE_CH_CONSERVATIVE = 0, GPE_CH_ADVECTIVE = 1 };
 
+/* Ablation switches of the 3-D flow discretisation, OR-ed together; 0 is the
+ * scheme of the paper.  The paper (Sec. 4, drop coalescence in 3-D) names
+ * both the transverse pressure average of the momentum equations' pressure
+ * gradient and the bulk viscosity eta_b = eta as needed for stable 3-D runs
+ * and demonstrates it by switching each off:
+ *  - GPE_SCHEME_NO_PAVG: the pressure gradient at a face is the plain
+ *    difference of the two cell pressures (no transverse average);
+ *  - GPE_SCHEME_NO_BULK: eta_b = 0, i.e. the term grad(eta_b div u) is
+ *    dropped from the momentum equations.
+ * Accepted for 3-D geometry only (GPE_EINVAL otherwise) and not by the
+ * batched ensemble. */
+enum gpe_scheme { GPE_SCHEME_PAPER = 0, GPE_SCHEME_NO_PAVG = 1, GPE_SCHEME_NO_BULK = 2 };
+
 /* Physical and numerical parameters in lattice units (dx = 1). */
 typedef struct gpe_params {
   int32_t geometry;        /* gpe_geometry                                             */
@@ -97,14 +110,15 @@ typedef struct gpe_params {
   double dt;               /* time step                                                */
   double cs2;              /* c_s^2 of the pressure equation                          */
   double rho_l, rho_g;     /* densities of liquid (phi = +1) and gas (phi = -1)       */
-  double eta_l, eta_g;     /* dynamic viscosities (bulk viscosity eta_b = eta)         */
+  double eta_l, eta_g;     /* dynamic viscosities (bulk viscosity eta_b = eta unless
+                              GPE_SCHEME_NO_BULK)                                      */
   double sigma;            /* surface tension of the force -sigma phi grad(mu)        */
   double mobility;         /* Cahn-Hilliard mobility M                                */
   double width;            /* interface width W: a = 3/(4W), kappa = 3W/8              */
   double g[3];             /* body force; buoyancy (rho(phi) - rho_ref) g              */
   double rho_ref;          /* reference density absorbed into the pressure            */
   int32_t init_kind;       /* gpe_init_kind (only when h_phi0 == NULL)                 */
-  int32_t reserved;
+  int32_t scheme;          /* gpe_scheme flags; 0 = the paper's scheme                  */
   double init_center[3];   /* cell-centre coordinates (x_c = i + 1/2)                  */
   double init_radius;
   double init_width;       /* profile width (usually = width)                          */
@@ -132,7 +146,7 @@ typedef struct gpe_problem {
   double Cn;               /* W / L_c                                                  */
   double G[3];             /* body force in units of U_c^2 / L_c                      */
   int32_t rho_ref_kind;    /* 0: rho_ref = 0, 1: rho_L, 2: rho_G                      */
-  int32_t reserved;
+  int32_t scheme;          /* gpe_scheme flags, copied to gpe_params                    */
 } gpe_problem;
 
 /* Diagnostics (FP64 reductions in a fixed order: bitwise reproducible). */

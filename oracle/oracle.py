@@ -103,6 +103,11 @@ def _params(prob: dict) -> _Params:
     P.flags = int(prob.get("flags", 0))
     if int(prob.get("ch_transport", 0)) == 1:  # the CH equation's advective form as printed
         P.flags |= ADVECTIVE_CH
+    scheme = int(prob.get("scheme", 0))  # ablations: 1 no pressure average, 2 no bulk viscosity
+    if scheme & 1:
+        P.flags |= NO_PAVG
+    if scheme & 2:
+        P.flags |= NO_BULK
     P.ch_rk = int(prob.get("ch_rk", 0))
     for key in ("dt", "cs2", "rho_l", "rho_g", "eta_l", "eta_g", "sigma", "mob", "width", "rho_ref"):
         setattr(P, key, float(prob[key]))

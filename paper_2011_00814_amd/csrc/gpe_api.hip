@@ -75,6 +75,8 @@ int validate(const gpe_params* p) {
     if (!std::isfinite(p->g[a])) return GPE_EINVAL;
   if (!std::isfinite(p->rho_ref)) return GPE_EINVAL;
   if (p->ch_transport != GPE_CH_CONSERVATIVE && p->ch_transport != GPE_CH_ADVECTIVE) return GPE_EINVAL;
+  if (p->scheme < 0 || p->scheme > (GPE_SCHEME_NO_PAVG | GPE_SCHEME_NO_BULK)) return GPE_EINVAL;
+  if (p->scheme != GPE_SCHEME_PAPER && dim != 3) return GPE_EINVAL;
   if (p->init_kind < 0 || p->init_kind > 4) return GPE_EINVAL;
   if (p->init_kind == GPE_INIT_ELLIPSE && (!(p->init_radius > 0) || !(std::fabs(p->init_amp) < 1.0)))
     return GPE_EINVAL;
@@ -204,7 +206,7 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
   mark();
   const int zf = flow_zchunk(s, sizeof(T));
   for (int st = 1; st <= 3; ++st) {
-    e = gpe::launch_flow<T>(flow_args<T>(s, st, zf), geom, st, s->stream);
+    e = gpe::launch_flow<T>(flow_args<T>(s, st, zf), geom, st, s->P.scheme, s->stream);
     mark();
     if (e != hipSuccess) return e;
   }
@@ -386,6 +388,7 @@ int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out) {
   for (int a = 0; a < 6; ++a) out->bc[a] = in->bc[a];
   out->lattice = in->lattice;
   out->ch_transport = in->ch_transport;
+  out->scheme = in->scheme;
   // dx = L_c / N_L = 1, dt = T_c / N_t = 1, U_c = L_c / T_c = N_L / N_t
   const double Uc = in->N_L / in->N_t;
   out->dt = 1.0;

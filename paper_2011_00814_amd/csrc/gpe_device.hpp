@@ -161,8 +161,9 @@ __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Launchers (explicitly instantiated for float and double).
+// scheme: gpe_scheme flags (non-zero ablation variants exist for 3-D only).
 template <typename T>
-hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, hipStream_t s);
+hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, int scheme, hipStream_t s);
 template <typename T>
 hipError_t launch_ch(const ChArgs<T>& a, int geometry, int stage, hipStream_t s);
 // Batches of 2-D / axisymmetric grids (geometry 0 / 1): one launch runs

@@ -25,6 +25,7 @@
 // (software pipelining).
 #include <type_traits>
 
+#include "gpe.h"
 #include "gpe_plane.hpp"
 
 namespace gpe {
@@ -37,8 +38,12 @@ template <typename T>
 struct FlowOcc { static constexpr int W = sizeof(T) == 4 ? 4 : 1; };
 
 // One work-group tile (btx, bty) x Z chunk btz of the grid described by A.
-template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+// SCH: gpe_scheme flags (0 = the paper's scheme; the others are ablations
+// that drop the transverse pressure average and / or the bulk viscosity).
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY, int SCH = 0>
 __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, int bty, int btz) {
+  constexpr bool PAVG = (SCH & GPE_SCHEME_NO_PAVG) == 0;
+  constexpr bool BULK = (SCH & GPE_SCHEME_NO_BULK) == 0;
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 3;                  // in-plane X range [-2, TX]
   constexpr int PY = (DIM == 3) ? TY + 3 : 1;  // in-plane Y range [-2, TY]
@@ -348,9 +353,11 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
         T V = T(2) * (eh * (UA0[ea] - ua) - el * (ua - UA0[-ea]));
         T Vt = AXI ? (Rk1 * EZp[0] - Rk * EZm[0]) * inv_rk : EZp[0] - EZm[0];
         if (DIM == 3) Vt += EB[eb] - EB[0];
-        V += T(0.25) * Vt + (eh * DV[0] - el * DV[-ea]);
+        const T Vb = BULK ? eh * DV[0] - el * DV[-ea] : T(0);  // bulk viscosity eta_b = eta
+        V += T(0.25) * Vt + Vb;
         // transversely averaged pressure gradient from the carried partial sums
-        const T G = (T(4) * g0 + (gp + gm)) * (DIM == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0));
+        const T G = PAVG ? (T(4) * g0 + (gp + gm)) * (DIM == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0))
+                         : P0[0] - P0[-ea];
         const T S = c.hsig * (phc + phl) * (MU[0] - MU[-ea]);
         const T B = (rho_f - c.rho_ref) * gA;
         return fma(T(-0.5), conv, (-G + V + S + B) * recip(rho_f));
@@ -389,9 +396,12 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
         }
         T Vt = XZm[1] - XZm[0];  // shear edge fluxes between planes k-1 and k
         if (DIM == 3) Vt += YZm[EY] - YZm[0];
-        V += T(0.25) * Vt + (eh * DV[0] - el * dv_prev);
+        const T Vb = BULK ? eh * DV[0] - el * dv_prev : T(0);
+        V += T(0.25) * Vt + Vb;
         T G;
-        if (DIM == 2) {
+        if (!PAVG) {
+          G = P0[0] - Pm[0];
+        } else if (DIM == 2) {
           G = (T(4) * (P0[0] - Pm[0]) + ((P0[1] - Pm[1]) + (P0[-1] - Pm[-1]))) * T(1.0 / 6.0);
         } else {
           auto row = [&](int o) {
@@ -457,11 +467,11 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
 }
 
 // Single grid: work-group b runs the tile tile_of_block assigns to it.
-template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY>
+template <typename T, int DIM, bool AXI, int STAGE, int TX, int TY, int SCH>
 __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_kernel(FlowArgs<T> A) {
   int btx, bty, btz;
   tile_of_block(A.g, btx, bty, btz);
-  flow_stage_tile<T, DIM, AXI, STAGE, TX, TY>(A, btx, bty, btz);
+  flow_stage_tile<T, DIM, AXI, STAGE, TX, TY, SCH>(A, btx, bty, btz);
 }
 
 // Batch of grids: work-group b runs tile tiles[b] = (case, btx, bty, btz)
@@ -475,33 +485,52 @@ __global__ __launch_bounds__(TX* TY, FlowOcc<T>::W) void flow_stage_batch_kernel
 }
 
 template <typename T, int DIM, bool AXI, int STAGE>
-static hipError_t launch_flow_t(const FlowArgs<T>& a, hipStream_t s) {
+static hipError_t launch_flow_t(const FlowArgs<T>& a, int scheme, hipStream_t s) {
   constexpr int TX = FlowTile<DIM, T>::TX, TY = FlowTile<DIM, T>::TY;
   FlowArgs<T> b = a;
   b.g.nb[0] = (a.g.n[0] + TX - 1) / TX;
   b.g.nb[1] = (a.g.n[1] + TY - 1) / TY;
   b.g.nb[2] = (a.g.n[2] + a.g.zchunk - 1) / a.g.zchunk;
   const unsigned nblk = (unsigned)(b.g.nb[0] * b.g.nb[1] * b.g.nb[2]);
-  hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, b);
+  const dim3 grid(nblk), block(TX * TY);
+  switch (scheme) {
+    case GPE_SCHEME_PAPER:
+      hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY, 0>), grid, block, 0, s, b);
+      break;
+    case GPE_SCHEME_NO_PAVG:  // ablation variants: 3-D only
+      if (DIM != 3) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY, DIM == 3 ? 1 : 0>), grid, block, 0, s, b);
+      break;
+    case GPE_SCHEME_NO_BULK:
+      if (DIM != 3) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY, DIM == 3 ? 2 : 0>), grid, block, 0, s, b);
+      break;
+    case GPE_SCHEME_NO_PAVG | GPE_SCHEME_NO_BULK:
+      if (DIM != 3) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((flow_stage_kernel<T, DIM, AXI, STAGE, TX, TY, DIM == 3 ? 3 : 0>), grid, block, 0, s, b);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <typename T, int DIM, bool AXI>
-static hipError_t launch_flow_g(const FlowArgs<T>& a, int stage, hipStream_t s) {
+static hipError_t launch_flow_g(const FlowArgs<T>& a, int stage, int scheme, hipStream_t s) {
   switch (stage) {
-    case 1: return launch_flow_t<T, DIM, AXI, 1>(a, s);
-    case 2: return launch_flow_t<T, DIM, AXI, 2>(a, s);
-    case 3: return launch_flow_t<T, DIM, AXI, 3>(a, s);
+    case 1: return launch_flow_t<T, DIM, AXI, 1>(a, scheme, s);
+    case 2: return launch_flow_t<T, DIM, AXI, 2>(a, scheme, s);
+    case 3: return launch_flow_t<T, DIM, AXI, 3>(a, scheme, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, hipStream_t s) {
+hipError_t launch_flow(const FlowArgs<T>& a, int geometry, int stage, int scheme, hipStream_t s) {
   switch (geometry) {
-    case 0: return launch_flow_g<T, 2, false>(a, stage, s);
-    case 1: return launch_flow_g<T, 2, true>(a, stage, s);
-    case 2: return launch_flow_g<T, 3, false>(a, stage, s);
+    case 0: return launch_flow_g<T, 2, false>(a, stage, scheme, s);
+    case 1: return launch_flow_g<T, 2, true>(a, stage, scheme, s);
+    case 2: return launch_flow_g<T, 3, false>(a, stage, scheme, s);
   }
   return hipErrorInvalidValue;
 }
@@ -531,8 +560,8 @@ hipError_t launch_flow_batch(const FlowArgs<T>* cases, const int4* tiles, int nt
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_flow<float>(const FlowArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_flow<double>(const FlowArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_flow<float>(const FlowArgs<float>&, int, int, int, hipStream_t);
+template hipError_t launch_flow<double>(const FlowArgs<double>&, int, int, int, hipStream_t);
 template hipError_t launch_flow_batch<float>(const FlowArgs<float>*, const int4*, int, int, int, hipStream_t);
 template hipError_t launch_flow_batch<double>(const FlowArgs<double>*, const int4*, int, int, int, hipStream_t);
 

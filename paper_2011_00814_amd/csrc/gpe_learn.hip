@@ -556,7 +556,6 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
   const int kg = lane / 32, col = lane % 32;
   const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
   const int ntiles = B * tiles_x * tiles_y;
-  const float sc[4] = {s0, s1, s2, s3};
 
   for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
     const int b = t / (tiles_x * tiles_y);
@@ -732,7 +731,6 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
       partial[t] = s;
     }
   }
-  (void)sc;
 }
 
 // per-case sums of the phi output from the per-tile sums, in tile order

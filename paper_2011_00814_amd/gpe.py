@@ -24,6 +24,7 @@ GPE_FIELD_P, GPE_FIELD_U, GPE_FIELD_V, GPE_FIELD_W, GPE_FIELD_PHI = 0, 1, 2, 3, 
 GPE_H2D, GPE_D2H = 0, 1
 GPE_INIT_NONE, GPE_INIT_DROP, GPE_INIT_BUBBLE, GPE_INIT_LAYER, GPE_INIT_ELLIPSE = 0, 1, 2, 3, 4
 GPE_CH_CONSERVATIVE, GPE_CH_ADVECTIVE = 0, 1
+GPE_SCHEME_PAPER, GPE_SCHEME_NO_PAVG, GPE_SCHEME_NO_BULK = 0, 1, 2
 
 i32, f64 = ctypes.c_int32, ctypes.c_double
 
@@ -34,7 +35,7 @@ class gpe_params(ctypes.Structure):
         ("lattice", i32), ("allow_unstable", i32), ("ch_transport", i32), ("dt", f64), ("cs2", f64),
         ("rho_l", f64), ("rho_g", f64), ("eta_l", f64), ("eta_g", f64),
         ("sigma", f64), ("mobility", f64), ("width", f64), ("g", f64 * 3), ("rho_ref", f64),
-        ("init_kind", i32), ("reserved", i32), ("init_center", f64 * 3), ("init_radius", f64),
+        ("init_kind", i32), ("scheme", i32), ("init_center", f64 * 3), ("init_radius", f64),
         ("init_width", f64), ("init_amp", f64),
     ]
 
@@ -44,7 +45,7 @@ class gpe_problem(ctypes.Structure):
         ("geometry", i32), ("precision", i32), ("n", i32 * 3), ("bc", i32 * 6),
         ("lattice", i32), ("capillary_scale", i32), ("ch_transport", i32), ("N_L", f64), ("N_t", f64),
         ("r_rho", f64), ("r_eta", f64), ("Re", f64), ("We", f64), ("Pe", f64), ("Cn", f64),
-        ("G", f64 * 3), ("rho_ref_kind", i32), ("reserved", i32),
+        ("G", f64 * 3), ("rho_ref_kind", i32), ("scheme", i32),
     ]
 
 
@@ -319,6 +320,7 @@ def params_from_problem(prob: dict) -> gpe_params:
     P.lattice = int(prob["lattice"])
     P.allow_unstable = int(prob.get("allow_unstable", 0))
     P.ch_transport = int(prob.get("ch_transport", GPE_CH_CONSERVATIVE))
+    P.scheme = int(prob.get("scheme", GPE_SCHEME_PAPER))
     P.dt, P.cs2 = float(prob["dt"]), float(prob["cs2"])
     P.rho_l, P.rho_g = float(prob["rho_l"]), float(prob["rho_g"])
     P.eta_l, P.eta_g = float(prob["eta_l"]), float(prob["eta_g"])

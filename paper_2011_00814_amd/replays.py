@@ -11,6 +11,10 @@ diagnostics, computed by the library's reduction kernels:
   in R, U_ci, T_ci; each case also records the other's length (the 3-D
   bridge radius on x = 0, the axisymmetric half length on the axis), so that
   the two geometries can be compared on the same flow;
+- the 3-D coalescence with each of the paper's two ablations of its scheme
+  (no transverse pressure average at Oh 0.3, zero bulk viscosity at
+  Oh 0.037) beside its control, with the largest grid-scale (checkerboard)
+  pressure amplitude, in units of the Laplace pressure 2 sigma / R;
 - Rayleigh-Taylor (At 0.5, Re 256 / 3000): bubble front (smallest crossing
   on y = 0) and spike front (largest crossing on y = 1/2), in L_c, T_c.
 
@@ -40,9 +44,29 @@ CASES = {
     "coalescence_axisym_oh0.119": (lambda p: W.coalescence_axisym(Oh=0.119, precision=p), 4.0, 20),
     "coalescence_axisym_oh0.3": (lambda p: W.coalescence_axisym(Oh=0.3, precision=p), 4.0, 20),
     "coalescence_3d_oh0.119": (lambda p: W.coalescence_3d_replay(Oh=0.119, precision=p), 4.0, 20),
+    # the paper's two ablations of the 3-D scheme, each beside its control:
+    # no transverse pressure average at Oh 0.3 (the paper's default D3Q15)
+    # and zero bulk viscosity at Oh 0.037
+    "coalescence_3d_oh0.3": (lambda p: W.coalescence_3d_replay(Oh=0.3, lattice=15, precision=p), 4.0, 20),
+    "coalescence_3d_oh0.3_nopavg": (
+        lambda p: W.coalescence_3d_replay(Oh=0.3, lattice=15, scheme=1, precision=p), 0.05, 50),
+    "coalescence_3d_oh0.037": (lambda p: W.coalescence_3d_replay(Oh=0.037, precision=p), 0.8, 16),
+    "coalescence_3d_oh0.037_nobulk": (
+        lambda p: W.coalescence_3d_replay(Oh=0.037, scheme=2, precision=p), 0.8, 16),
     "rt_re256": (lambda p: W.rt_paper(Re=256.0, precision=p), 4.5, 18),
     "rt_re3000": (lambda p: W.rt_paper(Re=3000.0, precision=p), 3.5, 14),
 }
+
+
+def checkerboard(p) -> float:
+    """Largest amplitude of the grid-scale (-1)^(i+j+k) mode of a 3-D field:
+    the alternating sum over each 2 x 2 x 2 block of cells, divided by 8 (a
+    pure checkerboard of amplitude A gives A; a smooth field gives a third
+    mixed derivative)."""
+    d = p[1:] - p[:-1]
+    d = d[:, 1:] - d[:, :-1]
+    d = d[:, :, 1:] - d[:, :, :-1]
+    return float(abs(d).max()) / 8.0
 
 
 def observe(name: str, s: G.Solver, prob: dict, sc: dict) -> dict:
@@ -65,6 +89,8 @@ def observe(name: str, s: G.Solver, prob: dict, sc: dict) -> dict:
         # bridge radius on the contact plane x = 0 (along y at z = 0): the
         # axisymmetric case's R_r
         out["R_neck"] = s.line_crossings(1, 0, 0)[1] / sc["L"]
+        # grid-scale pressure mode in units of the drop's Laplace pressure 2 sigma / R
+        out["p_cb"] = checkerboard(s.get("p")) / (2.0 * prob["sigma"] / sc["L"])
     elif name.startswith("rt"):
         ny = prob["n"][1]
         out["bubble"] = s.line_crossings(0, 0)[0] / sc["L"]

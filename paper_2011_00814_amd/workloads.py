@@ -396,13 +396,16 @@ def coalescence_axisym(NL=40, Oh=0.119, precision="fp64", N_t=None):
     return prob, st, scales
 
 
-def coalescence_3d_replay(NL=40, Oh=0.119, lattice=19, precision="fp64"):
+def coalescence_3d_replay(NL=40, Oh=0.119, lattice=19, precision="fp64", scheme=0):
     """The 3-D coalescence (Sec. 4) as a replay: the set-up of coalescence_3d
-    with the host-built initial field, reported in U_ci, T_ci like the
-    axisymmetric case.  D3Q19 by default: with D3Q15 the paper's parameters
-    lie beyond the RK4 stability limit of the CH sub-step."""
-    prob = coalescence_3d(n=int(3 * NL), Oh=Oh, lattice=lattice, precision=precision)
-    prob = dict(prob)
+    with the host-built initial field and the paper's N_t (10 N_L, 50 N_L for
+    Oh = 0.3), reported in U_ci, T_ci like the axisymmetric case.  D3Q19 by
+    default: with D3Q15 and N_t = 10 N_L the paper's parameters lie beyond the
+    RK4 stability limit of the CH sub-step.  scheme: gpe_scheme ablation
+    flags (1: no transverse pressure average, 2: zero bulk viscosity)."""
+    c = 50.0 if Oh >= 0.3 else 10.0
+    prob = coalescence_3d(n=int(3 * NL), Oh=Oh, lattice=lattice, precision=precision, N_t_per_L=c)
+    prob = dict(prob, scheme=scheme)
     prob.pop("init")
     st = coalescence_state(dict(prob, init={"center": (NL, 0.0, 0.0), "radius": float(NL),
                                             "width": prob["width"]}))

@@ -158,6 +158,27 @@ def test_advective_ch_transport(gpe, oracle, name, precision):
         _check(prob, out, ref, 1e-4, keys=["p", "u", "phi"])
 
 
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ablation_schemes_3d(gpe, oracle, scheme, precision):
+    """The 3-D ablation variants (1: no transverse pressure average, 2: zero
+    bulk viscosity, 3: both) against the oracle with the same switches."""
+    prob, st = _case("bubble3d_walls", seed=11, precision=precision)
+    prob["scheme"] = scheme
+    nsteps = 40
+    _say(f"[parity] bubble3d {precision} scheme={scheme} steps={nsteps}")
+    ref = oracle.run(prob, st, nsteps)
+    paper = oracle.run(dict(prob, scheme=0), st, nsteps)
+    # the switch changes the solution by far more than the parity tolerance
+    assert rel_l2(ref["u"], paper["u"]) > 1e-6
+    out, d = _run_gpu(gpe, prob, st, nsteps)
+    assert d["finite"] == 1
+    if precision == "fp64":
+        _check(prob, out, ref, 1e-11)
+    else:
+        _check(prob, out, ref, 1e-4, keys=["p", "u", "phi"])
+
+
 def test_diagnostics_match_oracle(gpe, oracle):
     for name in CASES:
         prob, st = _case(name)

@@ -103,6 +103,7 @@ def test_workspace_bytes(G):
     lambda P: setattr(P, "width", -1.0),
     lambda P: setattr(P, "rho_g", 0.0),
     lambda P: setattr(P, "ch_transport", 2),    # only 0 (conservative) and 1 (advective)
+    lambda P: setattr(P, "scheme", 1),          # ablation variants are 3-D only
 ])
 def test_invalid_params_rejected(G, mutate):
     prob, _ = W.static_drop_2d()
@@ -110,6 +111,13 @@ def test_invalid_params_rejected(G, mutate):
     assert G.gpe_workspace_bytes(P) > 0
     mutate(P)
     assert G.gpe_workspace_bytes(P) == 0
+
+
+@pytest.mark.parametrize("scheme,ok", [(0, True), (1, True), (2, True), (3, True), (4, False), (-1, False)])
+def test_scheme_flags_3d(G, scheme, ok):
+    prob, _ = W.rising_bubble_3d(nx=8, ny=8, nz=8)
+    P = G.params_from_problem(dict(prob, scheme=scheme))
+    assert (G.gpe_workspace_bytes(P) > 0) == ok
 
 
 def test_axisym_requires_axis_symmetry_bc(G):

@@ -64,3 +64,25 @@ def test_replay_cases_are_defined():
 
     for name, (build, t_end, n_out) in R.CASES.items():
         assert t_end > 0 and n_out > 0, name
+
+
+@pytest.mark.parametrize("Oh,Nt,scheme", [(0.037, 400, 2), (0.119, 400, 0), (0.3, 2000, 1)])
+def test_coalescence_3d_replay_groups(Oh, Nt, scheme):
+    p, st, sc = W.coalescence_3d_replay(NL=12, Oh=Oh, scheme=scheme)
+    NL = 12.0
+    assert p["n"] == (36, 36, 36) and p["bc"] == (W.SYMMETRY,) * 6 and p["scheme"] == scheme
+    assert abs(p["eta_l"] / math.sqrt(p["sigma"] * NL) - Oh) < 1e-12
+    # the paper's N_t = c N_L (c = 10, or 50 at Oh 0.3) steps per T_c, T_ci = T_c / Oh
+    assert abs(sc["T"] * Oh - Nt * NL / 40.0) < 1e-6
+
+
+def test_checkerboard_measure():
+    from paper_2011_00814_amd.replays import checkerboard
+
+    k, j, i = np.meshgrid(np.arange(6), np.arange(5), np.arange(7), indexing="ij")
+    cb = (-1.0) ** (i + j + k)
+    smooth = 0.3 + 0.1 * i - 0.2 * j + 0.05 * k + 0.01 * i * j + 0.02 * (i * i + k * k)
+    assert abs(checkerboard(2.5e-3 * cb) - 2.5e-3) < 1e-15
+    assert checkerboard(smooth) < 1e-15               # no i j k term: no response
+    assert abs(checkerboard(i * j * k * 1.0) - 1.0 / 8.0) < 1e-15  # third mixed derivative
+    assert abs(checkerboard(smooth + 1e-3 * cb) - 1e-3) < 1e-12
