@@ -1,6 +1,9 @@
 """Replays of the paper's experiments (Sec. 4) on the GPU with the paper's
 diagnostics, computed by the library's reduction kernels:
 
+- capillary wave (Sec. 4.1, Re 1000, r_rho = r_eta = 20) on the paper's two
+  meshes: the scaled interface displacement h~ = (h_eq - h_0) / A_p at
+  y = 0, in T_c;
 - falling drop (axisymmetric, Eo 144, Oh 0.0466): centroid velocity U_drop
   and aspect ratio Th / Wh (axial thickness over radial width), in
   U_c' = sqrt(g D), T_c' = sqrt(D / g);
@@ -39,6 +42,9 @@ def _falling(prec):
 
 CASES = {
     # name: (builder(precision) -> (prob, state, scales), end time in the case's time unit, outputs)
+    "capillary_wave": (lambda p: W.capillary_wave(precision=p), 30.0, 30),
+    "capillary_wave_fine": (
+        lambda p: W.capillary_wave(NL=128, Nt=1920, Cn=0.03125, Pe=4e4, precision=p), 30.0, 30),
     "falling_drop": (_falling, 12.0, 24),
     "coalescence_axisym_oh0.037": (lambda p: W.coalescence_axisym(Oh=0.037, precision=p), 4.0, 20),
     "coalescence_axisym_oh0.119": (lambda p: W.coalescence_axisym(Oh=0.119, precision=p), 4.0, 20),
@@ -73,7 +79,12 @@ def observe(name: str, s: G.Solver, prob: dict, sc: dict) -> dict:
     """The paper's diagnostics of case `name` for the current state of s."""
     st = s.phase_stats()
     out = {"volume": st["volume"]}
-    if name == "falling_drop":
+    if name.startswith("capillary_wave"):
+        # interface on the first cell row (y = 1/2 cell); the mode's amplitude
+        # there is cos(k / 2) times that on y = 0, where the paper measures it
+        h0 = s.line_crossings(0, 0)[0]
+        out["h_tilde"] = (sc["h_eq"] - h0) / (sc["A_p"] * math.cos(sc["k"] / 2.0))
+    elif name == "falling_drop":
         ext = s.interface_extent()
         out["U_drop"] = st["velocity"][0] / sc["U"]
         out["z_c"] = st["centroid"][0] / sc["L"]

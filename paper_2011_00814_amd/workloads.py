@@ -340,6 +340,31 @@ def coalescence_state(prob) -> dict:
 # Each returns (prob, state, scales): `scales` holds the length, velocity
 # and time units the paper reports its diagnostics in.
 # --------------------------------------------------------------------------
+def capillary_wave(NL=64, Nt=384, Cn=0.0625, Pe=2e4, Re=1000.0, ratio=20.0, precision="fp64"):
+    """Capillary wave in 2-D (Sec. 4.1): unit square with L_c = side length,
+    gas on the left, liquid on the right, no-slip walls at x = 0 and 1; the
+    lower half 0 <= y <= 1/2 with symmetry planes at y = 0 and 1/2; interface
+    h(y) = 1/2 + A_p cos(k (y + 1/2)), A_p = 0.01, k = 2 pi; Re = 1000,
+    r_rho = r_eta = 20 (equal kinematic viscosities), U_c = sigma / eta_L.
+    The paper's meshes: N_L = 64, N_t = 384, Cn = 1/16, Pe = 2e4 and the
+    refined N_L = 128, N_t = 1920, Cn = 1/32, Pe = 4e4.  Returns (prob,
+    state, scales) with the wave's A_p and k in lattice units."""
+    Uc = NL / Nt
+    eta_l = Uc * NL / Re
+    sigma = Uc * eta_l
+    W = Cn * NL
+    prob = base_problem(dim=2, n=(NL, NL // 2, 1), bc=(WALL, WALL, SYMMETRY, SYMMETRY, 0, 0),
+                        rho_l=1.0, rho_g=1.0 / ratio, eta_l=eta_l, eta_g=eta_l / ratio, sigma=sigma,
+                        mob=Uc * NL * NL / Pe, width=W, precision=precision)
+    x, y, _ = _centres(prob)
+    k = 2.0 * math.pi / NL
+    Ap = 0.01 * NL
+    st = zero_state(prob)
+    st["phi"] = np.tanh(2.0 * (x - (0.5 * NL + Ap * np.cos(k * (y + 0.5 * NL)))) / W)
+    scales = {"L": float(NL), "U": Uc, "T": float(Nt), "A_p": Ap, "k": k, "h_eq": 0.5 * NL}
+    return prob, st, scales
+
+
 def falling_drop_axisym(NL=50, precision="fp64", ch_transport=0):
     """Falling drop (Sec. 4): axisymmetric [0, 24 R] x [0, 8 R] (z, r) with
     L_c = R; the axis r = 0 is a symmetry line, the other three sides are

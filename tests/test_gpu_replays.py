@@ -166,3 +166,37 @@ def test_paper_ablations_3d_coalescence(gpe):
     assert all(row.get("finite", 1) == 1 for row in nob + ref)
     assert nob[-1]["p_cb"] > 1.0 and ref[-1]["p_cb"] < 0.01
     assert nob[-1]["p_cb"] > 100.0 * ref[-1]["p_cb"]
+
+
+def test_capillary_wave_meshes_against_prosperetti(gpe, oracle):
+    """The capillary wave (Sec. 4.1) on the paper's two meshes against the
+    closed-form solution over 30 T_c: the coarse mesh within the bounds the
+    oracle meets, the refined mesh closer to it (the paper's refinement
+    study), and the coarse series equal to the oracle's."""
+    from paper_2011_00814_amd import replays as R
+    from tests.closed_forms import prosperetti
+
+    def errors(name, series):
+        prob, _, sc = R.CASES[name][0]("fp64")
+        return [(row["t"], row["h_tilde"] - prosperetti(row["t"] * sc["T"], prob["sigma"], sc["k"],
+                                                         prob["rho_l"], prob["rho_g"], prob["eta_l"]))
+                for row in series[1:]]
+
+    _say("[replay] capillary wave N_L = 64 and 128, 30 T_c")
+    coarse = R.run("capillary_wave", "fp64")["series"]
+    fine = R.run("capillary_wave_fine", "fp64")["series"]
+    assert all(row.get("finite", 1) == 1 for row in coarse + fine)
+    ec, ef = errors("capillary_wave", coarse), errors("capillary_wave_fine", fine)
+    assert max(abs(e) for t, e in ec if t <= 3) < 0.06 and max(abs(e) for _, e in ec) < 0.13, ec
+    # measured: largest deviation 0.118 (N_L = 64) and 0.079 (N_L = 128)
+    assert max(abs(e) for _, e in ef) < 0.8 * max(abs(e) for _, e in ec), (ec, ef)
+    # the first 3 T_c of the coarse mesh against the oracle
+    prob, st, sc = R.CASES["capillary_wave"][0]("fp64")
+    state = st
+    for q in range(1, 4):
+        state = oracle.run(prob, state, int(sc["T"]))
+        row = state["phi"][0, 0]
+        i = int(np.where((row[:-1] < 0) & (row[1:] >= 0))[0][0])
+        h0 = i + 0.5 + row[i] / (row[i] - row[i + 1])
+        ref = (sc["h_eq"] - h0) / (sc["A_p"] * math.cos(sc["k"] / 2.0))
+        assert abs(coarse[q]["h_tilde"] - ref) < 1e-9, (q, coarse[q]["h_tilde"], ref)

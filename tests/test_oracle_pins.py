@@ -16,6 +16,7 @@ import pytest
 
 from oracle.oracle import FLOW_RK2, NO_BULK, NO_PAVG
 from paper_2011_00814_amd import workloads as W
+from tests.closed_forms import prosperetti
 
 
 def R3(z):  # TVD-RK3 amplification (Sec. 3, three-stage Shu-Osher form)
@@ -556,44 +557,17 @@ def test_laplace_static_drop(oracle):
 # P10: the paper's capillary-wave case against Prosperetti's closed-form
 # solution for equal kinematic viscosities (Sec. 4.1)
 # ---------------------------------------------------------------------------
-def prosperetti(t, sigma, k, rho_l, rho_g, nu):
-    from scipy.special import erfc, wofz
-    w0 = math.sqrt(sigma * k ** 3 / (rho_l + rho_g))
-    eps = nu * k * k / w0
-    beta = rho_l * rho_g / (rho_l + rho_g) ** 2
-    z = np.roots([1, -4 * beta * math.sqrt(eps * w0), 2 * (1 - 6 * beta) * eps * w0,
-                  4 * (1 - 3 * beta) * (eps * w0) ** 1.5, (1 - 4 * beta) * (eps * w0) ** 2 + w0 * w0])
-    tp = w0 * t
-    val = 4 * (1 - 4 * beta) * eps ** 2 / (8 * (1 - 4 * beta) * eps ** 2 + 1) * erfc(math.sqrt(eps * tp))
-    for i in range(4):
-        Zi = np.prod([z[j] - z[i] for j in range(4) if j != i])
-        # exp((z^2 - eps w0) t) erfc(z sqrt t) = exp(-eps w0 t) w(i z sqrt t)
-        val += (z[i] * w0 * w0 / (Zi * (z[i] ** 2 - eps * w0)) * math.exp(-eps * tp)
-                * wofz(1j * z[i] * math.sqrt(t))).real
-    return val
-
-
 def test_capillary_wave_prosperetti(oracle):
     import json
     import os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "capillary_wave.json")))
+    assert g["viscosity_ratio"] == g["density_ratio"] and g["wavelength"] == 1.0
+    assert g["h_eq"] == 0.5 and g["A_p"] == 0.01
     NL, Nt = g["N_L"], g["N_t"]
-    Uc = NL / Nt                       # dx = dt = 1
-    eta_l = Uc * NL / g["Re"]          # Re = rho_L U_c L_c / eta_L, rho_L = 1
-    sigma = Uc * eta_l                 # U_c = sigma / eta_L
-    Wd = g["Cn"] * NL
-    M = Uc * NL * NL / g["Pe"]         # Pe = U_c L_c^2 / (M sigma_ref)
-    rr = g["density_ratio"]
-    prob = W.base_problem(dim=2, n=(NL, NL // 2, 1), bc=(1, 1, 2, 2, 0, 0), rho_l=1.0,
-                          rho_g=1.0 / rr, eta_l=eta_l, eta_g=eta_l / g["viscosity_ratio"],
-                          sigma=sigma, mob=M, width=Wd)
+    prob, st, sc = W.capillary_wave(NL=NL, Nt=Nt, Cn=g["Cn"], Pe=g["Pe"], Re=g["Re"],
+                                    ratio=g["density_ratio"])
+    k, Ap, heq = sc["k"], sc["A_p"], sc["h_eq"]
     x = np.arange(NL) + 0.5
-    y = np.arange(NL // 2) + 0.5
-    X, Y = np.meshgrid(x, y)
-    k = 2 * math.pi / (g["wavelength"] * NL)
-    Ap, heq = g["A_p"] * NL, g["h_eq"] * NL
-    st = W.zero_state(prob)
-    st["phi"][0] = np.tanh(2 * (X - (heq + Ap * np.cos(k * (Y + NL / 2)))) / Wd)
 
     def interface_row0(phi):
         row = phi[0, 0]
@@ -607,7 +581,7 @@ def test_capillary_wave_prosperetti(oracle):
         t += chunk
         # row 0 sits half a cell above y = 0: divide out cos(k/2)
         num = (heq - interface_row0(state["phi"])) / (Ap * math.cos(k / 2))
-        errs.append((t / Nt, num - prosperetti(t, sigma, k, 1.0, 1.0 / rr, eta_l)))
+        errs.append((t / Nt, num - prosperetti(t, prob["sigma"], k, 1.0, prob["rho_g"], prob["eta_l"])))
     early = max(abs(e) for tt, e in errs if tt <= 3)
     full = max(abs(e) for _, e in errs)
     assert early < 0.06, errs
