@@ -56,7 +56,7 @@ CASES = {
     "coalescence_3d_oh0.3": (lambda p: W.coalescence_3d_replay(Oh=0.3, lattice=15, precision=p), 4.0, 20),
     "coalescence_3d_oh0.3_nopavg": (
         lambda p: W.coalescence_3d_replay(Oh=0.3, lattice=15, scheme=1, precision=p), 0.05, 50),
-    "coalescence_3d_oh0.037": (lambda p: W.coalescence_3d_replay(Oh=0.037, precision=p), 0.8, 16),
+    "coalescence_3d_oh0.037": (lambda p: W.coalescence_3d_replay(Oh=0.037, precision=p), 4.0, 20),
     "coalescence_3d_oh0.037_nobulk": (
         lambda p: W.coalescence_3d_replay(Oh=0.037, scheme=2, precision=p), 0.8, 16),
     "rt_re256": (lambda p: W.rt_paper(Re=256.0, precision=p), 4.5, 18),
