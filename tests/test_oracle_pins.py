@@ -586,3 +586,29 @@ def test_capillary_wave_prosperetti(oracle):
     full = max(abs(e) for _, e in errs)
     assert early < 0.06, errs
     assert full < 0.13, errs
+
+
+# ---------------------------------------------------------------------------
+# P11: the flow needs TVD-RK3 (Sec. 4, comparison of computation time: even
+# TVD-RK2 was not stable).  On the capillary-wave parameters the acoustic
+# amplification matrix (pressure equation, averaged pressure gradient,
+# viscous and bulk terms) has spectral radius > 1 somewhere in the
+# Brillouin zone under R2 and <= 1 everywhere under R3, and the oracle with
+# the RK2 switch blows up within half a T_c while RK3 stays bounded.
+# ---------------------------------------------------------------------------
+def test_flow_rk2_does_not_suffice(oracle):
+    prob, st, sc = W.capillary_wave()
+    N = 24
+    for rho, eta in ((prob["rho_l"], prob["eta_l"]), (prob["rho_g"], prob["eta_g"])):
+        r2 = r3 = 0.0
+        for a in range(N + 1):
+            for b in range(N + 1):
+                A = prob["dt"] * acoustic_matrix([math.pi * a / N, math.pi * b / N], rho, eta, prob["cs2"], 2)
+                r2 = max(r2, max(abs(np.linalg.eigvals(mat_R2(A)))))
+                r3 = max(r3, max(abs(np.linalg.eigvals(mat_R3(A)))))
+        assert r2 > 1.05 and r3 <= 1.0 + 1e-12, (rho, r2, r3)
+    half = int(sc["T"]) // 2
+    rk3 = oracle.run(prob, st, half)
+    assert np.all(np.isfinite(rk3["u"])) and np.max(np.abs(rk3["u"])) < 1e-3
+    rk2 = oracle.run(dict(prob, flags=FLOW_RK2), st, half)
+    assert not np.all(np.isfinite(rk2["u"])) or np.max(np.abs(rk2["u"])) > 1.0
