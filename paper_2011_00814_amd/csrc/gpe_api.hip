@@ -176,24 +176,29 @@ struct KernelTimer {
   int n = 0;
 };
 
+// Longest Z chunk per work-group (planes): see choose_zchunk.
+int zchunk_max(size_t esize) { return esize == 8 ? 128 : 64; }
+
 int flow_zchunk(const gpe_state* s, size_t esize) {
+  const int zmax = zchunk_max(esize);
   if (s->dim == 3)
     return esize == 8 ? gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, double>::TX, gpe::FlowTile<3, double>::TY,
-                                           gpe::FlowTile<3, double>::BPC, s->ncu)
+                                           gpe::FlowTile<3, double>::BPC, s->ncu, zmax)
                       : gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, float>::TX, gpe::FlowTile<3, float>::TY,
-                                           gpe::FlowTile<3, float>::BPC, s->ncu);
+                                           gpe::FlowTile<3, float>::BPC, s->ncu, zmax);
   return gpe::choose_zchunk(s->grid.n, gpe::FlowTile<2, float>::TX, gpe::FlowTile<2, float>::TY,
-                            gpe::FlowTile<2, float>::BPC, s->ncu);
+                            gpe::FlowTile<2, float>::BPC, s->ncu, zmax);
 }
 
 int ch_zchunk(const gpe_state* s, size_t esize) {
+  const int zmax = zchunk_max(esize);
   if (s->dim == 3)
     return esize == 8 ? gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, double>::TX, gpe::ChTile<3, double>::TY,
-                                           gpe::ChTile<3, double>::BPC, s->ncu)
+                                           gpe::ChTile<3, double>::BPC, s->ncu, zmax)
                       : gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, float>::TX, gpe::ChTile<3, float>::TY,
-                                           gpe::ChTile<3, float>::BPC, s->ncu);
+                                           gpe::ChTile<3, float>::BPC, s->ncu, zmax);
   return gpe::choose_zchunk(s->grid.n, gpe::ChTile<2, float>::TX, gpe::ChTile<2, float>::TY,
-                            gpe::ChTile<2, float>::BPC, s->ncu);
+                            gpe::ChTile<2, float>::BPC, s->ncu, zmax);
 }
 
 template <typename T>
