@@ -61,7 +61,7 @@ CASES = {
     "drop2d_periodic": lambda: W.static_drop_2d(n=70, R=14.0),
     "rt2d_walls": lambda: W.rayleigh_taylor_2d(nx=70, ny=150, amp_frac=0.05),
     "axisym_drop": lambda: W.axisym_drop(nz=100, nr=37, R=10.0, zc=45.0),
-    "bubble3d_walls": lambda: W.rising_bubble_3d(nx=40, ny=19, nz=40, R=7.0, zc=17.0, precision="fp64"),
+    "bubble3d_walls": lambda: W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0, precision="fp64"),
 }
 
 
@@ -133,7 +133,7 @@ def test_3d_lattices(gpe, oracle, lat):
     prob, st = _case("bubble3d_walls")
     prob["lattice"] = lat
     prob["bc"] = (0, 0, 2, 2, 1, 1)
-    st = W.perturbed(prob, W.rising_bubble_3d(nx=40, ny=19, nz=40, R=7.0, zc=17.0,
+    st = W.perturbed(prob, W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0,
                                                 precision="fp64")[1], 5, uamp=2e-3, pamp=2e-4)
     _say(f"[parity] bubble3d D3Q{lat} mixed BCs")
     ref = oracle.run(prob, st, 20)
