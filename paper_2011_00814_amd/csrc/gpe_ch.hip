@@ -75,41 +75,45 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   // arithmetic touches a loaded value before commit(), so the loads stay in
   // flight while the current plane is processed.  A plane index below -2
   // marks "nothing to stage".
-  T r_f[pm.NPASS], r_x[pm.NPASS], r_y[pm.NPASS], r_z[pm.NPASS];
-  auto fetch = [&](int kf, int kxy, int kz) {
+  constexpr int NP = PlaneMap<T, DIM, PX, PY, NT>::NPASS;
+  struct Staged {  // one iteration's loaded values, per load pass
+    T f[NP], x[NP], y[NP], z[NP];
+  };
+  Staged R;  // the values in flight in the main loop
+  auto fetch = [&](int kf, int kxy, int kz, Staged& r) {
     const ZMap<T> zf(g, kf), zxy(g, kxy), zz(g, kz);
     const T* __restrict__ bf = A.phi_in + zf.zc;
     const T* __restrict__ bx = A.usum[0] + zxy.zc;
     const T* __restrict__ by = A.usum[1] + zxy.zc;
     const T* __restrict__ bz = A.usum[2] + zz.zf;
 #pragma unroll
-    for (int p = 0; p < pm.NPASS; ++p) {
-      r_f[p] = r_x[p] = r_y[p] = r_z[p] = T(0);
+    for (int p = 0; p < NP; ++p) {
+      r.f[p] = r.x[p] = r.y[p] = r.z[p] = T(0);
       if (pm.ok[p]) {
         const auto q = pm.pos(g, p);
-        if (kf >= -2) r_f[p] = at(bf, q.oc);
+        if (kf >= -2) r.f[p] = at(bf, q.oc);
         if (!pm.inner_row(p)) continue;  // face sums are never read on the outermost row
         if (kxy >= -2) {
-          r_x[p] = at(bx, q.ox);
-          if (DIM == 3) r_y[p] = at(by, q.oy);
+          r.x[p] = at(bx, q.ox);
+          if (DIM == 3) r.y[p] = at(by, q.oy);
         }
-        if (kz >= -2) r_z[p] = at(bz, q.oc);
+        if (kz >= -2) r.z[p] = at(bz, q.oc);
       }
     }
   };
-  auto commit = [&](int kxy, int kz, int sf, int sz, bool do_f, bool do_xy, bool do_z) {
+  auto commit = [&](int kxy, int kz, int sf, int sz, bool do_f, bool do_xy, bool do_z, const Staged& r) {
     const ZMap<T> zxy(g, kxy), zz(g, kz);
 #pragma unroll
-    for (int p = 0; p < pm.NPASS; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int lp = (int)threadIdx.x + p * NT;
       if (lp >= PLANE) continue;
       const auto q = pm.pos(g, p);  // signs (all +1 inside an interior tile)
-      if (do_f) lds[(S_PH + sf) * PLANE + lp] = r_f[p];
+      if (do_f) lds[(S_PH + sf) * PLANE + lp] = r.f[p];
       if (do_xy) {
-        lds[S_SX * PLANE + lp] = r_x[p] * (q.sx * zxy.tan);
-        if (DIM == 3) lds[S_SY * PLANE + lp] = r_y[p] * (q.sy * zxy.tan);
+        lds[S_SX * PLANE + lp] = r.x[p] * (q.sx * zxy.tan);
+        if (DIM == 3) lds[S_SY * PLANE + lp] = r.y[p] * (q.sy * zxy.tan);
       }
-      if (do_z) lds[(S_SZ + sz) * PLANE + lp] = r_z[p] * (q.sz * zz.nrm);
+      if (do_z) lds[(S_SZ + sz) * PLANE + lp] = r.z[p] * (q.sz * zz.nrm);
     }
   };
 
@@ -340,9 +344,9 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   auto iter = [&](int k, auto sk) {
     constexpr int SK = decltype(sk)::value;  // slot of plane k
     constexpr int S1 = (SK + 1) % 3, S2 = (SK + 2) % 3;
-    commit(k + 1, k + 2, S2, S2, true, true, true);
+    commit(k + 1, k + 2, S2, S2, true, true, true, R);
     fetch_pt(k + 1, phis_next, acc_next);
-    if (k + 1 < z1) fetch(k + 3, k + 2, k + 3);  // in flight during this plane's work
+    if (k + 1 < z1) fetch(k + 3, k + 2, k + 3, R);  // in flight during this plane's work
     __syncthreads();
     derive(k + 1, std::integral_constant<int, S1>{});
     const T phc = L0[(S_PH + SK) * PLANE];
@@ -364,11 +368,15 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   };
 
   // -------- warm-up: phi(z0-2), phi(z0-1) and the Z sums of plane z0-1 ----
-  fetch(z0 - 2, -3, z0 - 1);
-  commit(-3, z0 - 1, 1, 2, true, false, true);
-  fetch(z0 - 1, -3, -3);
-  commit(-3, -3, 2, 0, true, false, false);
-  fetch(z0, z0 - 1, z0);
+  // (loads of both and of the first iteration issued before either commit)
+  {
+    Staged W0, W1;
+    fetch(z0 - 2, -3, z0 - 1, W0);
+    fetch(z0 - 1, -3, -3, W1);
+    fetch(z0, z0 - 1, z0, R);
+    commit(-3, z0 - 1, 1, 2, true, false, true, W0);
+    commit(-3, -3, 2, 0, true, false, false, W1);
+  }
   // iterations k = z0-2, z0-1 only stage and derive planes z0-1, z0
   for (int k = z0 - 2; k < z1; k += 3) {
     iter(k, std::integral_constant<int, 1>{});

@@ -78,8 +78,12 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // the derived eta and nu, into a ring slot.  No arithmetic touches a
   // loaded value before commit(), so the loads stay in flight while the
   // current plane is processed.
-  T r_p[pm.NPASS], r_x[pm.NPASS], r_y[pm.NPASS], r_z[pm.NPASS], r_f[pm.NPASS];
-  auto fetch = [&](int k) {
+  constexpr int NP = PlaneMap<T, DIM, PX, PY, NT>::NPASS;
+  struct Staged {  // one plane's loaded values, per load pass
+    T p[NP], x[NP], y[NP], z[NP], f[NP];
+  };
+  Staged R;  // the plane in flight in the main loop
+  auto fetch = [&](int k, Staged& r) {
     const ZMap<T> z(g, k);
     const T* __restrict__ bp = A.src[0] + z.zc;
     const T* __restrict__ bx = A.src[1] + z.zc;
@@ -87,34 +91,34 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     const T* __restrict__ bz = A.src[3] + z.zf;
     const T* __restrict__ bf = A.phi + z.zc;
 #pragma unroll
-    for (int p = 0; p < pm.NPASS; ++p) {
-      r_p[p] = r_x[p] = r_y[p] = r_z[p] = r_f[p] = T(0);
+    for (int p = 0; p < NP; ++p) {
+      r.p[p] = r.x[p] = r.y[p] = r.z[p] = r.f[p] = T(0);
       if (pm.ok[p]) {
         const auto q = pm.pos(g, p);
-        r_f[p] = at(bf, q.oc);
+        r.f[p] = at(bf, q.oc);
         if (pm.inner_row(p)) {  // p and u are never read on the outermost row
-          r_p[p] = at(bp, q.oc);
-          r_x[p] = at(bx, q.ox);
-          if (DIM == 3) r_y[p] = at(by, q.oy);
-          r_z[p] = at(bz, q.oc);
+          r.p[p] = at(bp, q.oc);
+          r.x[p] = at(bx, q.ox);
+          if (DIM == 3) r.y[p] = at(by, q.oy);
+          r.z[p] = at(bz, q.oc);
         }
       }
     }
   };
-  auto commit = [&](int s, int k) {
+  auto commit = [&](int s, int k, const Staged& r) {
     const ZMap<T> z(g, k);
     T* const e2 = lds + (k & 1) * PLANE;
 #pragma unroll
-    for (int p = 0; p < pm.NPASS; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int lp = (int)threadIdx.x + p * NT;
       if (lp >= PLANE) continue;
       const auto q = pm.pos(g, p);  // signs (all +1 inside an interior tile)
-      const T ph = r_f[p];
+      const T ph = r.f[p];
       const T eta = eta_of(c, ph);
-      lds[(S_P + s) * PLANE + lp] = r_p[p];
-      lds[(S_UX + s) * PLANE + lp] = r_x[p] * (q.sx * z.tan);
-      if (DIM == 3) lds[(S_UY + s) * PLANE + lp] = r_y[p] * (q.sy * z.tan);
-      lds[(S_UZ + s) * PLANE + lp] = r_z[p] * (q.sz * z.nrm);
+      lds[(S_P + s) * PLANE + lp] = r.p[p];
+      lds[(S_UX + s) * PLANE + lp] = r.x[p] * (q.sx * z.tan);
+      if (DIM == 3) lds[(S_UY + s) * PLANE + lp] = r.y[p] * (q.sy * z.tan);
+      lds[(S_UZ + s) * PLANE + lp] = r.z[p] * (q.sz * z.nrm);
       lds[(S_PH + s) * PLANE + lp] = ph;
       e2[S_ET * PLANE + lp] = eta;
       e2[S_NU * PLANE + lp] = eta * recip(rho_of(c, ph));
@@ -216,13 +220,18 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   };
 
   // -------- warm-up: planes z0-2, z0-1, z0 into slots 1, 2, 0 -------------
-  // (the ring slot of plane k is (k - z0) mod 3)
-  fetch(z0 - 2);
-  commit(1, z0 - 2);
-  fetch(z0 - 1);
-  commit(2, z0 - 1);
-  fetch(z0);
-  commit(0, z0);
+  // (the ring slot of plane k is (k - z0) mod 3).  The loads of all three
+  // are issued before the first is committed, so the warm-up waits for one
+  // memory latency, not three.
+  {
+    Staged W0, W1, W2;
+    fetch(z0 - 2, W0);
+    fetch(z0 - 1, W1);
+    fetch(z0, W2);
+    commit(1, z0 - 2, W0);
+    commit(2, z0 - 1, W1);
+    commit(0, z0, W2);
+  }
   __syncthreads();
   edges(z0 - 1, 2, 0, false);  // Z-directed edges between planes z0-1 and z0
   // eta and nu of the own cell on the previous plane (carried from plane to plane)
@@ -237,7 +246,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     gy_m = prow(L0 + (S_P + 2) * PLANE, EY, 1);
     gy_0 = prow(L0 + (S_P + 0) * PLANE, EY, 1);
   }
-  fetch(z0 + 1);
+  fetch(z0 + 1, R);
 
   // time level n at the thread's own cell (stages 2 and 3), loaded at the
   // top of the plane's step (before the next plane's loads, so that waiting
@@ -258,10 +267,10 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     constexpr int S0 = decltype(slots)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     __syncthreads();  // readers of slot SP (plane k-2) are done
-    commit(SP, k + 1);
+    commit(SP, k + 1, R);
     T qn_cur[4] = {T(0), T(0), T(0), T(0)};
     fetch_qn(k, qn_cur);
-    if (k + 1 < z1) fetch(k + 2);  // in flight during this plane's work
+    if (k + 1 < z1) fetch(k + 2, R);  // in flight during this plane's work
     __syncthreads();
 
     // mu and div u of plane k on [-1, T-1] (LDS positions 1 .. T+1)
