@@ -213,7 +213,6 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     const T* Y0 = Q0 + (S_FY + S0) * QPLANE;
     const T* Ym = Q0 + (S_FY + SM) * QPLANE;
     const T* Yp = Q0 + (S_FY + SP) * QPLANE;
-    const T* Z0 = Q0 + (S_FZ + S0) * QPLANE;
     const T* Zm = Q0 + (S_FZ + SM) * QPLANE;
     const T* Zp = Q0 + (S_FZ + SP) * QPLANE;
     T rp = T(1), rm = T(1), inv_r = T(1);

@@ -509,15 +509,6 @@ constexpr int kR1W = kTW + 4, kR1H = kTH + 4, kR1N = kR1W * kR1H;
 constexpr int kR2W = kTW + 2, kR2H = kTH + 2, kR2N = kR2W * kR2H;
 constexpr int kAS = 36;  // bf16 slots per pixel of a 32-channel region
 
-__device__ __forceinline__ mfma_bf16x4 unpack4(uint2 v) {
-  mfma_bf16x4 a;
-  a[0] = (short)(v.x & 0xffffu);
-  a[1] = (short)(v.x >> 16);
-  a[2] = (short)(v.y & 0xffffu);
-  a[3] = (short)(v.y >> 16);
-  return a;
-}
-
 // round to nearest even in one instruction (v_cvt_pk_bf16_f32); equal to
 // store(bf16&, float) except for the payload of a NaN
 __device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }

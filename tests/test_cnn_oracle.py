@@ -2,10 +2,8 @@
 against definitions written out independently: direct convolution loops,
 central finite differences, conservation identities of the restriction and
 exact crossings of linear profiles."""
-import math
 
 import numpy as np
-import pytest
 
 from oracle import cnn_oracle as C
 

@@ -2,10 +2,9 @@
 
 Tolerances: FP64 relative L2 <= 1e-11 after up to 1000 steps, FP32 <= 1e-4
 on u, p, phi; FP32 phase-mass drift < 1e-6 (relative to sum |phi_0|).
-Sizes span several work-group tiles (X tile 32 in 3-D, 64 in 2-D; Y tile 8;
-Z chunks of 32 / 16 planes) with ragged tails.
+Sizes span several work-group tiles (X tile 32 in 3-D, 64 in 2-D; Y tiles
+of 8 and 16; Z chunks of 8 planes, the last one ragged) with ragged tails.
 """
-import math
 import sys
 
 import numpy as np

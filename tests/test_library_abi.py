@@ -3,7 +3,6 @@ the library loads and exports every function include/gpe.h declares, the
 problem-statement mapping and workspace sizing behave as documented, and
 invalid parameter sets are rejected."""
 import ctypes
-import math
 
 import pytest
 
