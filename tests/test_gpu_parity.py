@@ -304,6 +304,39 @@ def test_full_size_256cubed_fp32_properties(gpe):
     assert np.max(np.abs(phi - phi[:, :, ::-1])) <= 1e-5
 
 
+def test_large_grid_1024cubed_fp32_properties(gpe):
+    """A grid past 2^32 bytes per field and 10^9 cells (82 GB of fields in
+    HBM; the benchmark physics with the in-kernel initial bubble): 64-bit
+    field offsets in the kernels, the copies and the reductions.  Three
+    steps stay finite, conserve the phase mass and keep the bubble
+    mirror-symmetric in x and y."""
+    import torch
+
+    import bench  # the repository root is on sys.path (conftest)
+
+    prob = bench.problem(1024, "fp32")
+    _say("[parity] 1024^3 fp32 properties (82 GB)")
+    s = gpe.Solver(prob, None)
+    d0 = s.diagnostics()
+    s.run(3)
+    s.synchronize()
+    d1 = s.diagnostics()
+    assert d1["finite"] == 1 and d1["step"] == 3
+    assert abs(d1["mass"] - d0["mass"]) / d0["mass_abs0"] < 1e-6
+    # planes through the bubble (centre z = 48, radius 16)
+    w = s.get("w")[24:73]
+    phi = s.get("phi")[24:73]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    sc = np.max(np.abs(w))
+    assert sc > 0
+    assert np.max(np.abs(w - w[:, :, ::-1])) <= 1e-4 * sc
+    assert np.max(np.abs(w - w[:, ::-1, :])) <= 1e-4 * sc
+    assert np.max(np.abs(phi - phi[:, :, ::-1])) <= 1e-5
+    assert np.min(phi) < -0.99 and np.max(phi) > 0.99
+
+
 # ---------------------------------------------------------------------------
 # The paper's 3-D coalescence set-up (reduced: N_L = 12, 36^3 cells).
 # ---------------------------------------------------------------------------
