@@ -270,6 +270,44 @@ def test_rest_state_bitwise_gpu(gpe):
 
 
 # ---------------------------------------------------------------------------
+# Degenerate sizes: the smallest grids the library accepts (3 cells on an
+# axis, so the halo of 2 wraps or mirrors onto the same few cells, one
+# ragged tile and a single Z chunk of 3 to 5 planes), every BC type, and a
+# run of zero steps.
+# ---------------------------------------------------------------------------
+MINIMAL = [
+    (2, (3, 3, 1), (0, 0, 0, 0, 0, 0), 9),
+    (2, (3, 4, 1), (1, 1, 1, 1, 0, 0), 9),
+    (2, (5, 3, 1), (2, 2, 1, 1, 0, 0), 9),
+    ("axi", (4, 3, 1), (1, 1, 2, 1, 0, 0), 9),
+    (3, (3, 3, 3), (0, 0, 0, 0, 0, 0), 15),
+    (3, (3, 4, 5), (1, 1, 1, 1, 1, 1), 19),
+    (3, (4, 3, 3), (2, 2, 0, 0, 1, 1), 27),
+]
+
+
+@pytest.mark.parametrize("dim,n,bc,lat", MINIMAL)
+def test_minimal_grids(gpe, oracle, dim, n, bc, lat):
+    prob = W.base_problem(dim=3 if dim == 3 else 2, n=n, bc=bc, lattice=lat, rho_l=1.0, rho_g=0.25,
+                          eta_l=0.03, eta_g=0.01, sigma=0.01, mob=0.02, g=(1e-4, -2e-4, 3e-4 if dim == 3 else 0.0))
+    if dim == "axi":
+        prob["axisym"] = 1
+        prob["g"] = (2e-4, 0.0, 0.0)
+    st = W.zero_state(prob)
+    st["phi"] = 0.3 + W.smooth_noise(st["phi"].shape, 5, 0.5)
+    st = W.perturbed(prob, st, 6, uamp=2e-3, pamp=2e-4)
+    _say(f"[parity] minimal grid {dim} n={n} bc={bc} D{lat}")
+    out0, _ = _run_gpu(gpe, prob, st, 0)
+    for k in out0:
+        if out0[k] is not None and st.get(k) is not None:
+            assert np.array_equal(out0[k], st[k]), k          # zero steps: the state unchanged
+    ref = oracle.run(prob, st, 12)
+    out, d = _run_gpu(gpe, prob, st, 12)
+    assert d["finite"] == 1
+    _check(prob, out, ref, 1e-11)
+
+
+# ---------------------------------------------------------------------------
 # Full size, benchmark launch configuration: 256^3 rising bubble, FP32.
 # ---------------------------------------------------------------------------
 def test_full_size_256cubed_fp32_one_step(gpe, oracle):
