@@ -612,3 +612,39 @@ def test_flow_rk2_does_not_suffice(oracle):
     assert np.all(np.isfinite(rk3["u"])) and np.max(np.abs(rk3["u"])) < 1e-3
     rk2 = oracle.run(dict(prob, flags=FLOW_RK2), st, half)
     assert not np.all(np.isfinite(rk2["u"])) or np.max(np.abs(rk2["u"])) > 1.0
+
+
+# ---------------------------------------------------------------------------
+# P12: observed orders on a smooth manufactured solution (the decaying shear
+# wave u_x = A sin(k y) exp(-nu k^2 t) of the incompressible equations, an
+# exact solution with zero pressure and zero convection): the error against
+# it falls as dt^3 at a fixed grid (TVD-RK3, Sec. 3) and as h^2 at a fixed
+# physical time with the time error negligible (the second-order staggered
+# viscous stencil, Sec. 3).
+# ---------------------------------------------------------------------------
+def _shear_wave_error(oracle, N, dt, tau, nu=0.05):
+    prob = W.base_problem(dim=2, n=(4, N, 1), rho_l=1.0, rho_g=1.0, eta_l=nu, eta_g=nu, mob=0.0, dt=dt)
+    st = W.zero_state(prob)
+    st["phi"][:] = 1.0
+    k = 2 * math.pi / N
+    A = 1e-3
+    y = np.arange(N) + 0.5
+    st["u"] = np.broadcast_to((A * np.sin(k * y)).reshape(1, N, 1), st["phi"].shape).copy()
+    nsteps = int(round(tau / (nu * k * k) / dt))
+    out = oracle.run(prob, st, nsteps)
+    t = nsteps * dt
+    semi = st["u"] * math.exp(-nu * (2 * math.sin(k / 2)) ** 2 * t)  # exact in time, discrete in space
+    pde = st["u"] * math.exp(-nu * k * k * t)                          # the PDE's solution
+    assert np.max(np.abs(out["p"])) == 0.0 and np.max(np.abs(out["v"])) == 0.0
+    return (np.max(np.abs(out["u"] - semi)) / A, np.max(np.abs(out["u"] - pde)) / A)
+
+
+def test_observed_orders_shear_wave(oracle):
+    # time: N = 16, tau = nu k^2 t = 0.5, dt = 8, 4, 2 against the semi-discrete solution
+    et = [_shear_wave_error(oracle, 16, dt, 0.5)[0] for dt in (8.0, 4.0, 2.0)]
+    rates_t = [math.log2(a / b) for a, b in zip(et, et[1:])]
+    assert all(2.9 < r < 3.1 for r in rates_t), (et, rates_t)
+    # space: N = 16, 32, 64 at tau = 0.5 with dt = 0.25 against the PDE solution
+    ex = [_shear_wave_error(oracle, N, 0.25, 0.5)[1] for N in (16, 32, 64)]
+    rates_x = [math.log2(a / b) for a, b in zip(ex, ex[1:])]
+    assert all(1.95 < r < 2.05 for r in rates_x), (ex, rates_x)
