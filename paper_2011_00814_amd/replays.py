@@ -1,6 +1,10 @@
 """Replays of the paper's experiments (Sec. 4) on the GPU with the paper's
 diagnostics, computed by the library's reduction kernels:
 
+- the benchmark configurations at full size and length: the static drop
+  (mass drift, kinetic energy, spurious velocity, pressure difference), the
+  Rayleigh-Taylor case (bubble and spike fronts) and the rising bubble (gas
+  centroid, top and bottom, rise velocity);
 - capillary wave (Sec. 4.1, Re 1000, r_rho = r_eta = 20) on the paper's two
   meshes: the scaled interface displacement h~ = (h_eq - h_0) / A_p at
   y = 0, in T_c;
@@ -40,8 +44,33 @@ def _falling(prec):
     return W.falling_drop_axisym(precision=prec)
 
 
+def _config1(prec):
+    prob, st = W.static_drop_2d(precision=prec)
+    return prob, st, {"L": 16.0, "U": 1.0, "T": 1.0}           # time in steps
+
+
+def _config2(prec):
+    prob, st = W.rayleigh_taylor_2d(precision=prec)
+    lam = float(prob["n"][0])
+    U = math.sqrt(-prob["g"][1] * lam)
+    return prob, st, {"L": lam, "U": U, "T": lam / U}            # T_c = lambda / sqrt(g lambda)
+
+
+def _config3(prec):
+    prob, st = W.rising_bubble_3d(precision=prec)
+    D = 32.0
+    g = -prob["g"][2]
+    return prob, st, {"L": D, "U": math.sqrt(g * D), "T": math.sqrt(D / g)}
+
+
 CASES = {
     # name: (builder(precision) -> (prob, state, scales), end time in the case's time unit, outputs)
+    # the benchmark configurations at full size and length: static drop 64^2 for 1000 steps,
+    # Rayleigh-Taylor 256 x 1024 for 20,000 steps (3.9 T_c), rising bubble 128 x 128 x 256 for
+    # 10,000 steps (9.4 T_c)
+    "config1_static_drop": (_config1, 1000.0, 10),
+    "config2_rt": (_config2, 20000.0 / 5120.0, 10),
+    "config3_rising_bubble": (_config3, 10000.0 / math.sqrt(32.0 / 2.8125e-5), 10),
     "capillary_wave": (lambda p: W.capillary_wave(precision=p), 30.0, 30),
     "capillary_wave_fine": (
         lambda p: W.capillary_wave(NL=128, Nt=1920, Cn=0.03125, Pe=4e4, precision=p), 30.0, 30),
@@ -79,7 +108,33 @@ def observe(name: str, s: G.Solver, prob: dict, sc: dict) -> dict:
     """The paper's diagnostics of case `name` for the current state of s."""
     st = s.phase_stats()
     out = {"volume": st["volume"]}
-    if name.startswith("capillary_wave"):
+    if name.startswith("config"):
+        d = s.diagnostics(check=False)
+        out.update(mass=d["mass"], mass_abs0=d["mass_abs0"], ke=d["ke"], umax=d["umax"] / sc["U"])
+    if name == "config1_static_drop":
+        p = s.get("p")
+        nx, ny = prob["n"][0], prob["n"][1]
+        R = math.sqrt(st["volume"] / math.pi)                   # radius of the liquid region
+        out["R_eff"] = R
+        out["dp_over_sigma_R"] = (p[0, ny // 2, nx // 2] - p[0, 0, 0]) / (prob["sigma"] / R)
+    elif name == "config2_rt":
+        nx = prob["n"][0]
+        # bubble (light fluid rising) on column x = 0, spike (heavy falling) on x = lambda / 2,
+        # relative to the initial mid-height, in lambda
+        y_mid = 0.5 * prob["n"][1]
+        out["bubble"] = (s.line_crossings(1, 0)[1] - y_mid) / sc["L"]
+        out["spike"] = (s.line_crossings(1, nx // 2)[0] - y_mid) / sc["L"]
+    elif name == "config3_rising_bubble":
+        nx, ny, nz = prob["n"]
+        ncell = float(nx * ny * nz)
+        vg = ncell - st["volume"]                               # gas cells
+        # gas centroid from the box's moment minus the liquid's; rise velocity
+        # of the gas as the closed box's zero net flux implies, -V_l w_l / V_g
+        out["z_gas"] = (ncell * 0.5 * nz - st["volume"] * st["centroid"][2]) / vg / sc["L"]
+        out["w_gas"] = -st["volume"] * st["velocity"][2] / vg / sc["U"]
+        ext = s.interface_extent()
+        out["z_bottom"], out["z_top"] = ext[2][0] / sc["L"], ext[2][1] / sc["L"]
+    elif name.startswith("capillary_wave"):
         # interface on the first cell row (y = 1/2 cell); the mode's amplitude
         # there is cos(k / 2) times that on y = 0, where the paper measures it
         h0 = s.line_crossings(0, 0)[0]
@@ -137,6 +192,8 @@ def run(name: str, precision: str = "fp64", t_end: float | None = None, n_out: i
     s.close()
     for row in series:
         row["volume"] = row["volume"] / vol0 if vol0 else math.nan
+        if "mass" in row:
+            row["mass_drift"] = abs(row["mass"] - series[0]["mass"]) / row["mass_abs0"]
     return {"case": name, "precision": precision, "grid": list(prob["n"]), "steps": done,
             "steps_per_time_unit": sc["T"], "wall_s": round(wall, 3),
             "mlups": round(nx * ny * nz * done / max(wall, 1e-9) / 1e6, 1), "series": series}

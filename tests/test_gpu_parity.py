@@ -321,6 +321,29 @@ def test_full_size_256cubed_fp32_one_step(gpe, oracle):
     assert drift < 1e-6
 
 
+def test_config2_rayleigh_taylor_full_size(gpe, oracle):
+    """Configuration 2 at its full size (256 x 1024, walls and periodic x),
+    FP64 and FP32, against the oracle."""
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4)):
+        prob, st = W.rayleigh_taylor_2d(precision=prec)
+        _say(f"[parity] Rayleigh-Taylor 256 x 1024 {prec} 20 steps")
+        ref = oracle.run(prob, st, 20)
+        out, d = _run_gpu(gpe, prob, st, 20)
+        assert d["finite"] == 1
+        _check(prob, out, ref, tol, keys=None if prec == "fp64" else ["p", "u", "phi"])
+
+
+def test_config3_rising_bubble_full_size(gpe, oracle):
+    """Configuration 3 at its full size (128 x 128 x 256, walls), FP32,
+    against the oracle."""
+    prob, st = W.rising_bubble_3d(precision="fp32")
+    _say("[parity] rising bubble 128 x 128 x 256 fp32 3 steps")
+    ref = oracle.run(prob, st, 3)
+    out, d = _run_gpu(gpe, prob, st, 3)
+    assert d["finite"] == 1
+    _check(prob, out, ref, 1e-4, keys=["p", "u", "phi"])
+
+
 def test_full_size_256cubed_fp32_properties(gpe):
     """Properties that hold at any size: phase mass conserved and the state
     finite over 50 graph-replayed steps; bubble mirror-symmetric in x and y."""

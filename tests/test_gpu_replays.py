@@ -201,3 +201,40 @@ def test_capillary_wave_meshes_against_prosperetti(gpe, oracle):
         h0 = i + 0.5 + row[i] / (row[i] - row[i + 1])
         ref = (sc["h_eq"] - h0) / (sc["A_p"] * math.cos(sc["k"] / 2.0))
         assert abs(coarse[q]["h_tilde"] - ref) < 1e-9, (q, coarse[q]["h_tilde"], ref)
+
+
+def test_baseline_configs_full_length(gpe):
+    """The three benchmark configurations at full size and length: the
+    static drop 64^2 (1000 steps, FP64), Rayleigh-Taylor 256 x 1024 (20,000
+    steps, FP64 and FP32) and the rising bubble 128 x 128 x 256 (10,000
+    steps, FP32), with the quantities they record."""
+    from paper_2011_00814_amd import replays as R
+
+    _say("[replay] configuration 1: static drop 64^2, 1000 steps")
+    c1 = R.run("config1_static_drop", "fp64")["series"]
+    assert all(row.get("finite", 1) == 1 for row in c1)
+    assert max(row["mass_drift"] for row in c1) < 1e-12
+    assert c1[-1]["umax"] < 1e-3                    # spurious currents decay (measured 9e-5)
+
+    _say("[replay] configuration 2: Rayleigh-Taylor 256 x 1024, 20,000 steps")
+    rt = {p: R.run("config2_rt", p)["series"] for p in ("fp64", "fp32")}
+    a = rt["fp64"]
+    assert all(row.get("finite", 1) == 1 for row in a + rt["fp32"])
+    assert max(row["mass_drift"] for row in a) < 1e-12
+    assert max(row["mass_drift"] for row in rt["fp32"]) < 5e-6
+    assert all(q["bubble"] > p["bubble"] for p, q in zip(a, a[1:]))   # the bubble rises
+    assert all(q["spike"] < p["spike"] for p, q in zip(a, a[1:]))     # the spike falls faster
+    assert a[-1]["bubble"] > 0.7 and a[-1]["spike"] < -1.1            # measured 0.797, -1.274
+    for p, q in zip(a, rt["fp32"]):
+        assert abs(p["bubble"] - q["bubble"]) < 1e-3 and abs(p["spike"] - q["spike"]) < 1e-3
+
+    _say("[replay] configuration 3: rising bubble 128 x 128 x 256, 10,000 steps")
+    b = R.run("config3_rising_bubble", "fp32")["series"]
+    assert all(row.get("finite", 1) == 1 for row in b)
+    assert max(row["mass_drift"] for row in b) < 5e-6
+    z = [row["z_gas"] for row in b]
+    t = [row["t"] for row in b]
+    assert all(q > p for p, q in zip(z, z[1:]))
+    rise = [(z2 - z1) / (t2 - t1) for z1, z2, t1, t2 in zip(z[1:], z[2:], t[1:], t[2:])]
+    assert all(0.5 < v < 0.7 for v in rise), rise   # measured 0.57-0.58 sqrt(g D) after 1 T_c
+    assert b[-1]["z_top"] < 8.0                      # below the top wall (8 D)
