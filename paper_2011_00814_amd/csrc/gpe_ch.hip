@@ -185,7 +185,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
 
   // pointwise stage inputs (phi* and the RK4 running sum) at the thread's
   // own cell, loaded one plane ahead of their use
-  constexpr bool NEED_PHIS = STAGE == CH_RK2_2 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3;
+  constexpr bool NEED_PHIS = STAGE == CH_RK2_2 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
   constexpr bool NEED_ACC = STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
   T phis_cur = T(0), acc_cur = T(0), phis_next = T(0), acc_next = T(0);
   // advective form: 4 u_hat of the own cell (sums over its two faces) of the
@@ -315,20 +315,24 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     } else if (STAGE == CH_RK2_2) {
       out = ps + T(0.5) * ((phc - ps) + dt * L);
     } else if (STAGE == CH_RK4_1) {
+      // classic RK4 with increments a, b, c, d = dt L; the running sum holds
+      // the increments only, a + 2b + 2c + d, so phi* is rounded together
+      // with the whole step's increment once (near phi = +-1 a small
+      // increment would otherwise be rounded away at every stage)
       const T kk = dt * L;
       out = fma(T(0.5), kk, phc);
-      acc = fma(kk, T(1.0 / 6.0), phc);
+      acc = kk;
     } else if (STAGE == CH_RK4_2) {
       const T kk = dt * L;
       out = fma(T(0.5), kk, ps);
-      acc = fma(kk, T(1.0 / 3.0), ac);
+      acc = fma(T(2), kk, ac);
     } else if (STAGE == CH_RK4_3) {
       const T kk = dt * L;
       out = ps + kk;
-      acc = fma(kk, T(1.0 / 3.0), ac);
+      acc = fma(T(2), kk, ac);
     } else {
       const T kk = dt * L;
-      out = fma(kk, T(1.0 / 6.0), ac);
+      out = ps + (ac + kk) / T(6);
     }
   };
 

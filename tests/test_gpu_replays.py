@@ -231,7 +231,7 @@ def test_baseline_configs_full_length(gpe):
     _say("[replay] configuration 3: rising bubble 128 x 128 x 256, 10,000 steps")
     b = R.run("config3_rising_bubble", "fp32")["series"]
     assert all(row.get("finite", 1) == 1 for row in b)
-    assert max(row["mass_drift"] for row in b) < 5e-6
+    assert max(row["mass_drift"] for row in b) < 2e-7     # measured 4.8e-8 after 10,000 steps
     z = [row["z_gas"] for row in b]
     t = [row["t"] for row in b]
     assert all(q > p for p, q in zip(z, z[1:]))
