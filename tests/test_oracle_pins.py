@@ -589,7 +589,7 @@ def test_capillary_wave_prosperetti(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P11: the flow needs TVD-RK3 (Sec. 4, comparison of computation time: even
+# P13: the flow needs TVD-RK3 (Sec. 4, comparison of computation time: even
 # TVD-RK2 was not stable).  On the capillary-wave parameters the acoustic
 # amplification matrix (pressure equation, averaged pressure gradient,
 # viscous and bulk terms) has spectral radius > 1 somewhere in the
@@ -615,7 +615,7 @@ def test_flow_rk2_does_not_suffice(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P12: observed orders on a smooth manufactured solution (the decaying shear
+# P14: observed orders on a smooth manufactured solution (the decaying shear
 # wave u_x = A sin(k y) exp(-nu k^2 t) of the incompressible equations, an
 # exact solution with zero pressure and zero convection): the error against
 # it falls as dt^3 at a fixed grid (TVD-RK3, Sec. 3) and as h^2 at a fixed
