@@ -107,6 +107,45 @@ def cpu_baseline(n: int, precision: str, z_sample: int = 64, steps: int = 4):
     }
 
 
+def cpu_configs() -> dict:
+    """The oracle timed on all host cores and on one core for bounded samples
+    of each benchmark configuration (context for the GPU figures, never a
+    target): MLUPS over a few steps from the configuration's initial state."""
+    import ctypes
+
+    from oracle import oracle as O
+    from paper_2011_00814_amd import workloads as W
+
+    gomp = ctypes.CDLL("libgomp.so.1")
+    nmax = int(gomp.omp_get_max_threads())
+    cases = [
+        ("configuration 1: static drop 64^2", W.static_drop_2d(), (200, 50)),
+        ("configuration 2: Rayleigh-Taylor 256 x 1024", W.rayleigh_taylor_2d(), (20, 4)),
+        ("configuration 3: rising bubble 128 x 128 x 256", W.rising_bubble_3d(precision="fp64"), (2, 1)),
+        ("256^3 rising bubble, 256 x 256 x 64 slab", W.rising_bubble_3d(nx=256, ny=256, nz=64, zc=48.0,
+                                                                       precision="fp64"), (2, 1)),
+    ]
+    rows = []
+    try:
+        for name, (prob, st), steps in cases:
+            cells = prob["n"][0] * prob["n"][1] * prob["n"][2]
+            row = {"case": name, "cells": cells}
+            for threads, nsteps in ((nmax, steps[0]), (1, steps[1])):
+                gomp.omp_set_num_threads(threads)
+                t0 = time.perf_counter()
+                O.run(prob, st, nsteps)
+                dt = time.perf_counter() - t0
+                key = "all_cores" if threads == nmax else "one_core"
+                row[key] = {"threads": threads, "steps": nsteps, "s": round(dt, 2),
+                            "mlups": round(cells * nsteps / dt / 1e6, 3)}
+                print(f"cpu_configs: {name}, {threads} thread(s): {row[key]['mlups']} MLUPS",
+                      file=sys.stderr, flush=True)
+            rows.append(row)
+    finally:
+        gomp.omp_set_num_threads(nmax)
+    return {"kind": "oracle", "precision": "fp64", "cores": nmax, "rows": rows}
+
+
 def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_steps: int = 200) -> dict:
     """The batched ensemble of 512 seeded 2-D drops: aggregate throughput of
     `steps` graph-replayed batch steps, per-case finite flags after them, and
@@ -329,6 +368,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the CPU oracle on every configuration, all cores and one core (about 2 min)")
     ap.add_argument("--workload", choices=("bubble3d", "ensemble", "learned", "coalescence"), default="bubble3d")
     ap.add_argument("--learned-summary", type=int, default=1,
                     help="include a reduced learned-correction run in the default line (0: skip)")
@@ -478,6 +519,8 @@ def main():
         line["learned"] = learned_bench(ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n, args.precision)
+    if args.cpu_configs:
+        line["cpu_configs"] = cpu_configs()
     print(json.dumps(line), flush=True)
 
 
