@@ -5,7 +5,7 @@
  * state, trained on restrictions of the solver's own fine-grid runs.  The
  * network and its training are not part of the paper's method; the paper's
  * Sec. 4 Rayleigh-Taylor set-up supplies the flows it is trained and
- * judged on, and the plain fine-grid solver (include/gpe.h) stays the
+ * evaluated on, and the plain fine-grid solver (include/gpe.h) stays the
  * reference and the fallback.
  *
  * Network: three 3 x 3 convolutions, channels 4 -> 32 -> 32 -> 4, ReLU after

@@ -5,7 +5,7 @@
  * flows using general pressure equation" (arXiv 2011.00814).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
- * judge of the GPU path.  Only the test-suite, the smoke check and the
+ * reference the GPU path is checked against.  Only the test-suite, the smoke check and the
  * CPU-baseline leg of the benchmark may load it.  It shares no code, header,
  * table or helper with the GPU library, and the GPU library never calls it.
  *

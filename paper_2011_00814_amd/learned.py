@@ -1,5 +1,5 @@
 """Learned coarse-grid correction on one GPU: training data from the solver's
-own fine runs, training, and the judgement against the fine solver.
+own fine runs, training, and the evaluation against the fine solver.
 
 Orchestration only.  The fine and coarse runs are batched ensembles
 (gpe_ensemble_*), restriction, targets, the network, its training and the

@@ -1,7 +1,7 @@
 """The learned coarse correction end to end on the GPU, at a small size
 (fine 64 x 128, coarse 16 x 32, one coarse step = 4 fine steps): data from
 the solver's own fine runs, training on the GPU, a gain over the plain
-coarse solver on flows it has not seen, and the rollout judged against the
+coarse solver on flows it has not seen, and the rollout evaluated against the
 fine solver."""
 import math
 import sys
