@@ -419,3 +419,37 @@ def test_coalescence_3d_against_oracle_and_symmetry(gpe, oracle, lat):
     tr = lambda a: np.transpose(a, (1, 0, 2))  # noqa: E731  (z, y, x) -> (y, z, x)
     assert np.max(np.abs(out["phi"] - tr(out["phi"]))) < 1e-12
     assert np.max(np.abs(out["v"] - tr(out["w"]))) < 1e-12 * max(1e-30, np.max(np.abs(out["v"])))
+
+
+# ---------------------------------------------------------------------------
+# Observed orders on the GPU path (FP64): the decaying shear wave, an exact
+# solution of the incompressible equations, converges as dt^3 in time
+# (TVD-RK3) and as h^2 in space at fixed physical time.
+# ---------------------------------------------------------------------------
+def test_observed_orders_gpu(gpe):
+    def error(N, dt, tau=0.5, nu=0.05):
+        prob = W.base_problem(dim=2, n=(4, N, 1), rho_l=1.0, rho_g=1.0, eta_l=nu, eta_g=nu, mob=0.0, dt=dt)
+        # dt = 8 and 4 exceed the acoustic limit of the stability estimate, but
+        # the shear wave is exactly divergence-free and p stays exactly 0, so no
+        # acoustic mode is ever excited
+        prob["allow_unstable"] = 1
+        st = W.zero_state(prob)
+        st["phi"][:] = 1.0
+        k = 2 * np.pi / N
+        A = 1e-3
+        y = np.arange(N) + 0.5
+        st["u"] = np.broadcast_to((A * np.sin(k * y)).reshape(1, N, 1), st["phi"].shape).copy()
+        nsteps = int(round(tau / (nu * k * k) / dt))
+        out, _ = _run_gpu(gpe, prob, st, nsteps)
+        assert np.max(np.abs(out["p"])) == 0.0
+        t = nsteps * dt
+        semi = st["u"] * np.exp(-nu * (2 * np.sin(k / 2)) ** 2 * t)
+        pde = st["u"] * np.exp(-nu * k * k * t)
+        return np.max(np.abs(out["u"] - semi)) / A, np.max(np.abs(out["u"] - pde)) / A
+
+    et = [error(16, dt)[0] for dt in (8.0, 4.0, 2.0)]
+    rt = [np.log2(a / b) for a, b in zip(et, et[1:])]
+    assert all(2.9 < r < 3.1 for r in rt), (et, rt)
+    ex = [error(N, 0.25)[1] for N in (16, 32, 64)]
+    rx = [np.log2(a / b) for a, b in zip(ex, ex[1:])]
+    assert all(1.95 < r < 2.05 for r in rx), (ex, rx)
