@@ -548,10 +548,14 @@ int orc_run(const orc_params* P, double* p, double* u, double* v, double* w,
     /* ---- CH sub-step with the centre velocity frozen ---- */
     const double* w3 = dim == 3 ? uh[2] : NULL;
     if (ch_rk == 2) {
+      /* TVD-RK2 as phi* + (a + b)/2 with the increments a = dt L(phi*),
+       * b = dt L(phi* + a): the stage-1 increment is kept rather than
+       * recovered as (phi* + a) - phi* (the same form as RK4 below) */
+      double* ka = acc;
       orc_ch_rhs(P, phi, uh[0], uh[1], w3, Lph);
-      for (size_t c = 0; c < N; ++c) ph1[c] = phi[c] + dt * Lph[c];
+      for (size_t c = 0; c < N; ++c) { ka[c] = dt * Lph[c]; ph1[c] = phi[c] + ka[c]; }
       orc_ch_rhs(P, ph1, uh[0], uh[1], w3, Lph);
-      for (size_t c = 0; c < N; ++c) phi[c] = phi[c] + 0.5 * ((ph1[c] - phi[c]) + dt * Lph[c]);
+      for (size_t c = 0; c < N; ++c) phi[c] = phi[c] + 0.5 * (ka[c] + dt * Lph[c]);
     } else {
       /* classic RK4: a, b, c, d increments; the sum (a + 2b + 2c + d)/6 */
       double* ka = acc;              /* a, then running weighted sum */

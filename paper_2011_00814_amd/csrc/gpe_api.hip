@@ -31,7 +31,7 @@ void needed(const gpe_params* p, bool need[B_COUNT]) {
   if (dim == 2) {
     need[B_Q0 + 2] = need[B_Q1 + 2] = need[B_Q2 + 2] = false;  // no Y velocity
     need[B_US + 1] = false;
-    need[B_PHB] = need[B_ACC] = false;                         // RK2 only
+    need[B_PHB] = false;                                       // RK2 only
   }
 }
 
@@ -591,7 +591,7 @@ int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, 
                               "ch_rk2_stage2"};
   // algorithmic HBM traffic per launch, in fields of one cell
   const double f3[7] = {9, 13, 16, 6, 8, 8, 7};
-  const double f2[5] = {7, 10, 12, 4, 5};
+  const double f2[5] = {7, 10, 12, 5, 6};
   // all steps are enqueued back to back (no host synchronisation between
   // them), then read once
   std::vector<hipEvent_t> ev((size_t)nsteps * (nk + 1), nullptr);

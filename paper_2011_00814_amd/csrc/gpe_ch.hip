@@ -186,7 +186,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   // pointwise stage inputs (phi* and the RK4 running sum) at the thread's
   // own cell, loaded one plane ahead of their use
   constexpr bool NEED_PHIS = STAGE == CH_RK2_2 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
-  constexpr bool NEED_ACC = STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
+  constexpr bool NEED_ACC = STAGE == CH_RK2_2 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3 || STAGE == CH_RK4_4;
   T phis_cur = T(0), acc_cur = T(0), phis_next = T(0), acc_next = T(0);
   // advective form: 4 u_hat of the own cell (sums over its two faces) of the
   // plane being written and of the next one
@@ -311,9 +311,14 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     T& acc = at(A.acc + po, ij);
     const T dt = c.dt;
     if (STAGE == CH_RK2_1) {
-      out = fma(dt, L, phc);
+      // TVD-RK2 as phi* + (a + b)/2 with a = dt L kept in the running-sum
+      // buffer (not recovered as (phi* + a) - phi*, which near phi = +-1
+      // drops the part of a below half an ulp)
+      const T kk = dt * L;
+      out = phc + kk;
+      acc = kk;
     } else if (STAGE == CH_RK2_2) {
-      out = ps + T(0.5) * ((phc - ps) + dt * L);
+      out = ps + T(0.5) * (ac + dt * L);
     } else if (STAGE == CH_RK4_1) {
       // classic RK4 with increments a, b, c, d = dt L; the running sum holds
       // the increments only, a + 2b + 2c + d, so phi* is rounded together

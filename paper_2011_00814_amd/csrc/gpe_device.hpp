@@ -74,7 +74,7 @@ struct ChArgs {
   const T* phi_in;  // phase field the RHS is evaluated on (read with halo 2)
   const T* usum[3]; // u^n + u^{n+1} on faces (centre velocity = 1/4 of the face pair sum)
   const T* phis;    // phi* (start of the sub-step), read pointwise
-  T* acc;           // RK4 running sum of the increments a + 2b + 2c + d
+  T* acc;           // running sum of the increments: a (RK2), a + 2b + 2c + d (RK4)
   T* out;           // next stage input or the new phi*
   int adv;          // 1: convection u_hat . grad(phi); 0: div(phi u_hat)
 };

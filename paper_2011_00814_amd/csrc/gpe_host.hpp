@@ -21,7 +21,7 @@ enum Buf {
   B_PHI = 12, // phi*
   B_PHA = 13, // CH stage buffer A
   B_PHB = 14, // CH stage buffer B (RK4)
-  B_ACC = 15, // RK4 running sum
+  B_ACC = 15, // running sum of the CH stage increments (RK2 and RK4)
   B_US = 16,  // u^n + u^{n+1} on X, Y, Z faces      (3 slots)
   B_SCR = 19, // reduction scratch
   B_COUNT = 20

@@ -221,7 +221,7 @@ def test_baseline_configs_full_length(gpe):
     a = rt["fp64"]
     assert all(row.get("finite", 1) == 1 for row in a + rt["fp32"])
     assert max(row["mass_drift"] for row in a) < 1e-12
-    assert max(row["mass_drift"] for row in rt["fp32"]) < 5e-6
+    assert max(row["mass_drift"] for row in rt["fp32"]) < 1e-6   # measured 2.9e-7 over 20,000 steps
     assert all(q["bubble"] > p["bubble"] for p, q in zip(a, a[1:]))   # the bubble rises
     assert all(q["spike"] < p["spike"] for p, q in zip(a, a[1:]))     # the spike falls faster
     assert a[-1]["bubble"] > 0.7 and a[-1]["spike"] < -1.1            # measured 0.797, -1.274

@@ -84,8 +84,8 @@ def test_workspace_bytes(G):
     P = G.params_from_problem(prob)
     n = 64 * 64 * 8
     align = lambda b: (b + 255) // 256 * 256
-    # 2-D: 3 state + 3 + 3 stage fields, phi*, one CH stage buffer, 2 face sums
-    assert G.gpe_workspace_bytes(P) == 13 * align(n) + align((512 * 8 + 8) * 8)
+    # 2-D: 3 state + 3 + 3 stage fields, phi*, one CH stage buffer, the kept CH increment, 2 face sums
+    assert G.gpe_workspace_bytes(P) == 14 * align(n) + align((512 * 8 + 8) * 8)
     prob3, _ = W.rising_bubble_3d(nx=256, ny=256, nz=256, precision="fp32")
     P3 = G.params_from_problem(prob3)
     n3 = 256 ** 3 * 4
