@@ -139,3 +139,30 @@ def test_full_ensemble_workload_runs(gpe):
         assert d1["step"] == 50
         assert abs(d1["mass"] - d["mass"]) / d["mass_abs0"] < 1e-6, i
     ens.close()
+
+
+def test_full_ensemble_configured_length(gpe):
+    """The 512-case workload over its configured 5000 steps: every per-case
+    finite flag agrees with that case's own diagnostics (a sample plus every
+    flagged case), all cases stay finite, and phase mass is conserved in the
+    sampled cases."""
+    cases = W.ensemble_cases(512, seed=0)
+    ens = gpe.Ensemble(cases)
+    sample = list(range(0, 512, 23))
+    d0 = {i: ens.case(i).diagnostics() for i in sample}
+    ens.run(5000)
+    ens.synchronize()
+    flags = ens.finite()
+    bad = [i for i in range(512) if not flags[i]]
+    _say(f"[ensemble] 512 cases, finite after 5000 steps: {int(flags.sum())}; flagged: {bad[:20]}")
+    drift = 0.0
+    for i in sorted(set(sample) | set(bad)):
+        d1 = ens.case(i).diagnostics()
+        assert d1["step"] == 5000
+        assert bool(d1["finite"]) == bool(flags[i]), i
+        if i in d0 and flags[i]:
+            drift = max(drift, abs(d1["mass"] - d0[i]["mass"]) / d0[i]["mass_abs0"])
+    _say(f"[ensemble] max relative mass drift over the sample: {drift:.2e}")
+    assert not bad
+    assert drift < 1e-5
+    ens.close()
