@@ -308,17 +308,19 @@ def test_minimal_grids(gpe, oracle, dim, n, bc, lat):
 
 
 # ---------------------------------------------------------------------------
-# Full size, benchmark launch configuration: 256^3 rising bubble, FP32.
+# Full size, benchmark launch configuration: 256^3 rising bubble, FP32 (the
+# headline) and FP64, every field compared.
 # ---------------------------------------------------------------------------
-def test_full_size_256cubed_fp32_one_step(gpe, oracle):
-    prob, st = W.rising_bubble_3d(nx=256, ny=256, nz=256, zc=48.0, precision="fp32")
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-11)])
+def test_full_size_256cubed_one_step(gpe, oracle, precision, tol):
+    prob, st = W.rising_bubble_3d(nx=256, ny=256, nz=256, zc=48.0, precision=precision)
     st = W.perturbed(prob, st, 7, uamp=2e-3, pamp=2e-4)
-    _say("[parity] 256^3 fp32 one step vs oracle")
+    _say(f"[parity] 256^3 {precision} one step vs oracle")
     out, d = _run_gpu(gpe, prob, st, 1, graph=False)
     ref = oracle.run(prob, st, 1)
-    _check(prob, out, ref, 1e-4)
+    _check(prob, out, ref, tol)
     drift = abs(d["mass"] - oracle.diagnostics(prob, st)["mass"]) / d["mass_abs0"]
-    assert drift < 1e-6
+    assert drift < (1e-6 if precision == "fp32" else 1e-13)
 
 
 def test_config2_rayleigh_taylor_full_size(gpe, oracle):
