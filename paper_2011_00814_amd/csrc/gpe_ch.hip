@@ -57,6 +57,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = btx * TX, y0 = bty * TY;
   const int z0 = btz * g.zchunk;
+  __builtin_assume(z0 >= 0);  // lets the plane-index checks of the staging fold
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
@@ -74,7 +75,11 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   // commit() applies the ghost-rule signs and writes them to LDS.  No
   // arithmetic touches a loaded value before commit(), so the loads stay in
   // flight while the current plane is processed.  A plane index below -2
-  // marks "nothing to stage".
+  // marks "nothing to stage" (only in the warm-up, where the indices are
+  // constants).  Every lane issues every load, so no branch separates the
+  // loads from the waits for them: a position outside the mapped halo
+  // (never read) loads the plane's first element instead, and the face sums
+  // are loaded on the outermost row too (never read there either).
   constexpr int NP = PlaneMap<T, DIM, PX, PY, NT>::NPASS;
   struct Staged {  // one iteration's loaded values, per load pass
     T f[NP], x[NP], y[NP], z[NP];
@@ -88,17 +93,13 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     const T* __restrict__ bz = A.usum[2] + zz.zf;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      r.f[p] = r.x[p] = r.y[p] = r.z[p] = T(0);
-      if (pm.ok[p]) {
-        const auto q = pm.pos(g, p);
-        if (kf >= -2) r.f[p] = at(bf, q.oc);
-        if (!pm.inner_row(p)) continue;  // face sums are never read on the outermost row
-        if (kxy >= -2) {
-          r.x[p] = at(bx, q.ox);
-          if (DIM == 3) r.y[p] = at(by, q.oy);
-        }
-        if (kz >= -2) r.z[p] = at(bz, q.oc);
-      }
+      const auto q = pm.pos(g, p);
+      const bool ok = pm.ok[p];
+      const int oc = ok ? q.oc : 0;
+      r.f[p] = (kf >= -2) ? at(bf, oc) : T(0);
+      r.x[p] = (kxy >= -2) ? at(bx, ok ? q.ox : 0) : T(0);
+      r.y[p] = (DIM == 3 && kxy >= -2) ? at(by, ok ? q.oy : 0) : T(0);
+      r.z[p] = (kz >= -2) ? at(bz, oc) : T(0);
     }
   };
   auto commit = [&](int kxy, int kz, int sf, int sz, bool do_f, bool do_xy, bool do_z, const Staged& r) {
@@ -191,12 +192,13 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   // advective form: 4 u_hat of the own cell (sums over its two faces) of the
   // plane being written and of the next one
   T uc_cur[3] = {T(0), T(0), T(0)}, uc_next[3] = {T(0), T(0), T(0)};
+  // (unconditional: outside the chunk, or in an inactive lane, it loads a
+  // value of the chunk that is never used)
   auto fetch_pt = [&](int k, T& ps, T& ac) {
-    if (active && k >= z0 && k < z1) {
-      const size_t po = (size_t)k * ny * nx;
-      if (NEED_PHIS) ps = at(A.phis + po, ij);
-      if (NEED_ACC) ac = at(A.acc + po, ij);
-    }
+    const size_t po = (size_t)min(max(k, z0), z1 - 1) * ny * nx;
+    const int o = active ? ij : 0;
+    if (NEED_PHIS) ps = at(A.phis + po, o);
+    if (NEED_ACC) ac = at(A.acc + po, o);
   };
 
   // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP);
@@ -354,7 +356,11 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     constexpr int S1 = (SK + 1) % 3, S2 = (SK + 2) % 3;
     commit(k + 1, k + 2, S2, S2, true, true, true, R);
     fetch_pt(k + 1, phis_next, acc_next);
-    if (k + 1 < z1) fetch(k + 3, k + 2, k + 3, R);  // in flight during this plane's work
+    {  // in flight during this plane's work; the chunk's last plane loads the
+       // planes just loaded again (unused) so that the loads are unconditional
+      const int d = (k + 1 < z1) ? 1 : 0;
+      fetch(k + 2 + d, k + 1 + d, k + 2 + d, R);
+    }
     __syncthreads();
     derive(k + 1, std::integral_constant<int, S1>{});
     const T phc = L0[(S_PH + SK) * PLANE];

@@ -63,6 +63,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = btx * TX, y0 = bty * TY;
   const int z0 = btz * g.zchunk;
+  __builtin_assume(z0 >= 0);  // lets the plane-index conditions of the staging fold
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
@@ -83,6 +84,11 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     T p[NP], x[NP], y[NP], z[NP], f[NP];
   };
   Staged R;  // the plane in flight in the main loop
+  // Every lane issues every load, so no branch separates the loads from the
+  // waits for them: a position outside the mapped halo (never read) loads
+  // the plane's first element instead, and on the outermost row, where p and
+  // u are never read, an interior tile loads them from the next row (cache
+  // lines fetched anyway) and a boundary tile from the mapped position.
   auto fetch = [&](int k, Staged& r) {
     const ZMap<T> z(g, k);
     const T* __restrict__ bp = A.src[0] + z.zc;
@@ -92,17 +98,15 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     const T* __restrict__ bf = A.phi + z.zc;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      r.p[p] = r.x[p] = r.y[p] = r.z[p] = r.f[p] = T(0);
-      if (pm.ok[p]) {
-        const auto q = pm.pos(g, p);
-        r.f[p] = at(bf, q.oc);
-        if (pm.inner_row(p)) {  // p and u are never read on the outermost row
-          r.p[p] = at(bp, q.oc);
-          r.x[p] = at(bx, q.ox);
-          if (DIM == 3) r.y[p] = at(by, q.oy);
-          r.z[p] = at(bz, q.oc);
-        }
-      }
+      const auto q = pm.pos(g, p);
+      const bool ok = pm.ok[p];
+      const int oc = ok ? q.oc : 0;
+      const int dq = (DIM == 3 && pm.interior && !pm.inner_row(p)) ? nx : 0;
+      r.f[p] = at(bf, oc);
+      r.p[p] = at(bp, oc + dq);
+      r.x[p] = at(bx, (ok ? q.ox : 0) + dq);
+      r.y[p] = (DIM == 3) ? at(by, (ok ? q.oy : 0) + dq) : T(0);
+      r.z[p] = at(bz, oc + dq);
     }
   };
   auto commit = [&](int s, int k, const Staged& r) {
@@ -252,8 +256,8 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // top of the plane's step (before the next plane's loads, so that waiting
   // for it in the update does not also wait for those)
   auto fetch_qn = [&](int k, T* dst) {
-    if (STAGE >= 2 && active) {
-      const size_t ci = (size_t)k * ny * nx + ij;
+    if (STAGE >= 2) {  // an inactive lane loads the plane's first element (unused)
+      const size_t ci = (size_t)k * ny * nx + (active ? ij : 0);
 #pragma unroll
       for (int f = 0; f < 4; ++f)
         if (DIM == 3 || f != 2) dst[f] = (STAGE == 3 ? A.dst[f] : A.qn[f])[ci];
@@ -270,7 +274,9 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     commit(SP, k + 1, R);
     T qn_cur[4] = {T(0), T(0), T(0), T(0)};
     fetch_qn(k, qn_cur);
-    if (k + 1 < z1) fetch(k + 2, R);  // in flight during this plane's work
+    // in flight during this plane's work; the chunk's last plane loads plane
+    // k + 1 again (just loaded, unused) so that the loads are unconditional
+    fetch(k + 1 < z1 ? k + 2 : k + 1, R);
     __syncthreads();
 
     // mu and div u of plane k on [-1, T-1] (LDS positions 1 .. T+1)
