@@ -201,6 +201,23 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     if (NEED_ACC) ac = at(A.acc + po, o);
   };
 
+  // FP64: the values of plane k are stored one iteration later, right after
+  // the next plane's commit and before its loads; a store issued after the
+  // loads sits behind a branch (warm-up iterations and ragged lanes store
+  // nothing), and the compiler would then wait for it together with the
+  // loads at the next commit (measured: the FP64 stages 4-6 % faster, FP32
+  // stages 0.5 % slower, so FP32 stores at once).
+  constexpr bool DEFER = sizeof(T) == 8;
+  T pv_out = T(0), pv_acc = T(0);
+  constexpr bool WRITES_ACC = STAGE == CH_RK2_1 || STAGE == CH_RK4_1 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3;
+  auto store = [&](int k) {
+    if (k >= z0 && active) {
+      const size_t po = (size_t)k * ny * nx;
+      at(A.out + po, ij) = pv_out;
+      if (WRITES_ACC) at(A.acc + po, ij) = pv_acc;
+    }
+  };
+
   // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP);
   // phc = phi(k) at the own cell
   auto output = [&](int k, auto s0, T phc, T ps, T ac, T ucx, T ucy, T ucz) {
@@ -308,9 +325,8 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     // L = -3 sum_i w_i e_i . F(x + e_i) + 6 M sum_i w_i (mu_i - mu); the
     // stored fluxes carry 4x the centre velocity
     const T L = T(-0.75) * flux + T(6) * c.mob * lap;
-    const size_t po = (size_t)k * ny * nx;
-    T& out = at(A.out + po, ij);
-    T& acc = at(A.acc + po, ij);
+    T& out = pv_out;
+    T& acc = pv_acc;
     const T dt = c.dt;
     if (STAGE == CH_RK2_1) {
       // TVD-RK2 as phi* + (a + b)/2 with a = dt L kept in the running-sum
@@ -341,6 +357,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
       const T kk = dt * L;
       out = ps + (ac + kk) / T(6);
     }
+    if (!DEFER) store(k);
   };
 
   // one iteration: stage phi(k+2), the X/Y sums of plane k+1 and the Z sums
@@ -355,6 +372,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     constexpr int SK = decltype(sk)::value;  // slot of plane k
     constexpr int S1 = (SK + 1) % 3, S2 = (SK + 2) % 3;
     commit(k + 1, k + 2, S2, S2, true, true, true, R);
+    if (DEFER) store(k - 1);
     fetch_pt(k + 1, phis_next, acc_next);
     {  // in flight during this plane's work; the chunk's last plane loads the
        // planes just loaded again (unused) so that the loads are unconditional
@@ -397,6 +415,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     if (k + 1 < z1) iter(k + 1, std::integral_constant<int, 2>{});
     if (k + 2 < z1) iter(k + 2, std::integral_constant<int, 0>{});
   }
+  if (DEFER) store(z1 - 1);
 }
 
 // Single grid: work-group b runs the tile tile_of_block assigns to it.
