@@ -262,7 +262,15 @@ static double face_rhs(const grid_t* g, int a, ix3 x, const double* p,
   double V;
   const double eta_hi = Sc(g, eta, x), eta_lo = Sc(g, eta, lo);
   const double ua_p = Fv(g, vel[a], a, sh(x, a, 1)), ua_m = Fv(g, vel[a], a, sh(x, a, -1));
-  if (axi && a == 1) {
+  const int printed = axi && (P->flags & ORC_AXI_PRINTED);
+  if (axi && a == 1 && printed) {
+    /* radial face, the r-equation as printed: d_r(2 eta d_r u_r) plus
+     * (eta/r)(d_r u_r - u_r/r), d_r u_r by the central difference of the
+     * two neighbouring radial faces, eta of the face the mean of its cells */
+    const double R = rf(x.v[1]);
+    V = 2.0 * (eta_hi * (ua_p - ua) - eta_lo * (ua - ua_m));
+    V += 0.5 * (eta_lo + eta_hi) / R * (0.5 * (ua_p - ua_m) - ua / R);
+  } else if (axi && a == 1) {
     /* radial face at radius R_j: (1/r) d_r(r 2 eta d_r u_r) - 2 eta u_r / r^2 */
     const int j = x.v[1];
     const double R = rf(j);
@@ -279,7 +287,14 @@ static double face_rhs(const grid_t* g, int a, ix3 x, const double* p,
                       (Fv(g, vel[b], b, sh(x, b, 1)) - Fv(g, vel[b], b, sh(lo, b, 1))));
     double fm = em * ((ua - Fv(g, vel[a], a, sh(x, b, -1))) +
                       (Fv(g, vel[b], b, x) - Fv(g, vel[b], b, lo)));
-    if (axi && b == 1) {
+    if (axi && b == 1 && printed) {
+      /* axial face, the z-equation as printed: d_r[eta (d_r u_z + d_z u_r)]
+       * plus (eta/r) d_r u_z, d_r u_z by the central difference of the two
+       * radial neighbours, eta of the face the mean of its cells */
+      V += fp - fm;
+      V += 0.5 * (eta_lo + eta_hi) / rc(x.v[1]) * 0.5 *
+           (Fv(g, vel[a], a, sh(x, b, 1)) - Fv(g, vel[a], a, sh(x, b, -1)));
+    } else if (axi && b == 1) {
       /* axial face: (1/r) d_r [ r eta (d_r u_z + d_z u_r) ] */
       const int j = x.v[1];
       V += (rf(j + 1) * fp - rf(j) * fm) / rc(j);

@@ -33,7 +33,11 @@ enum {
   ORC_NO_PAVG      = 1,  /* pressure gradient without transverse averaging  */
   ORC_NO_BULK      = 2,  /* bulk viscosity eta_b = 0 instead of eta          */
   ORC_FLOW_RK2     = 4,  /* TVD-RK2 instead of TVD-RK3 for (p, u)            */
-  ORC_ADVECTIVE_CH = 8   /* CH transport in advective form u.grad(phi)       */
+  ORC_ADVECTIVE_CH = 8,  /* CH transport in advective form u.grad(phi)       */
+  ORC_AXI_PRINTED  = 16  /* axisymmetric viscous terms in the form printed in
+                            Sec. 2 (Cartesian stress differences plus
+                            (eta/r) d_r u_z and (eta/r)(d_r u_r - u_r/r))
+                            instead of the exact cylindrical form            */
 };
 
 typedef struct {

@@ -28,7 +28,7 @@ _SRC = os.path.join(_HERE, "gpe_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 BC = {"periodic": 0, "wall": 1, "symmetry": 2}
-NO_PAVG, NO_BULK, FLOW_RK2, ADVECTIVE_CH = 1, 2, 4, 8
+NO_PAVG, NO_BULK, FLOW_RK2, ADVECTIVE_CH, AXI_PRINTED = 1, 2, 4, 8, 16
 
 
 class _Params(ctypes.Structure):
