@@ -99,8 +99,8 @@ def test_ensemble_case_against_oracle(gpe, oracle):
     for i, prob in enumerate(cases):
         _say(f"[ensemble] oracle parity case {i} n={prob['n']} dt={prob['dt']:.4g}")
         ref = oracle.run(prob, W.ensemble_state(prob), 30)
-        errs = compare_states(prob, ens.case(i).state(), ref)
-        assert all(v <= 1e-11 for v in errs.values()), (i, errs)
+        errs, raw = compare_states(prob, ens.case(i).state(), ref)
+        assert all(v <= 1e-11 for v in errs.values()), (i, errs, raw)
     ens.close()
 
 

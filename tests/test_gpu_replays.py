@@ -94,8 +94,8 @@ def test_reduced_replays_match_oracle(gpe, oracle, name):
     s.synchronize()
     out = s.state()
     s.close()
-    errs = compare_states(prob, out, ref)
-    assert all(e <= 1e-11 for e in errs.values()), errs
+    errs, raw = compare_states(prob, out, ref)
+    assert all(e <= 1e-11 for e in errs.values()), (errs, raw)
 
 
 @pytest.mark.parametrize("name,frac", [("falling_drop", 0.1), ("coalescence_axisym_oh0.119", 0.1),
