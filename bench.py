@@ -61,9 +61,7 @@ def csrc_hash() -> str:
 def problem(n: int, precision: str):
     from paper_2011_00814_amd import workloads as W
 
-    prob, _ = W.rising_bubble_3d(nx=4, ny=4, nz=4, precision=precision)  # parameters only
-    prob = dict(prob, n=(n, n, n))
-    prob["init"] = {"kind": 2, "center": (n / 2, n / 2, 48.0), "radius": 16.0, "width": prob["width"]}
+    prob, _ = W.rising_bubble_3d(nx=n, ny=n, nz=n, zc=48.0, precision=precision, in_kernel_init=True)
     return prob
 
 

@@ -125,28 +125,67 @@ typedef struct gpe_params {
   double init_amp;
 } gpe_params;
 
-/* The paper's problem statement (Sec. 4 set-up): characteristic length L_c
- * resolved by N_L cells, characteristic time T_c = L_c / U_c resolved by N_t
- * steps, so that dx = dt = 1, U_c = N_L / N_t and c_s^2 = 1/3. */
+/* The paper's problem statement (Sec. 4 set-ups).  The characteristic
+ * length L_c is resolved by N_L cells and the characteristic time
+ * T_c = L_c / U_c by N_t steps, so that dx = dt = 1 in lattice units,
+ * U_c = N_L / N_t and c_s^2 = 1/3 (c_s = dx / (sqrt(3) dt), Sec. 2);
+ * rho_L = 1 and sigma_ref = 1 (Sec. 2, chemical potential).  The groups
+ * that fix eta_L, sigma and g come in the alternatives below; the length
+ * in Oh, Eo and Mo is L_g = L_g_factor L_c (the paper uses the drop
+ * diameter 2 L_c in some set-ups and the radius in others). */
+enum gpe_time_scale {
+  GPE_TIME_NT = 0,       /* U_c = N_L / N_t                                           */
+  GPE_TIME_MA = 1        /* U_c = Ma c_s (Mach number of the characteristic velocity) */
+};
+enum gpe_visc_group {
+  GPE_VISC_RE = 0,       /* Re = rho_L U_c L_c / eta_L                                */
+  GPE_VISC_OH = 1,       /* Oh = eta_L / sqrt(rho_L sigma L_g)                        */
+  GPE_VISC_MO = 2,       /* Mo = g (rho_L - rho_G) eta_L^4 / (rho_L^2 sigma^3)        */
+  GPE_VISC_CAPILLARY = 3 /* U_c = sigma / eta_L: eta_L = sigma / U_c                  */
+};
+enum gpe_st_group {
+  GPE_ST_NONE = 0,       /* sigma = 0                                                 */
+  GPE_ST_WE = 1,         /* We = rho_L U_c^2 L_c / sigma                              */
+  GPE_ST_EO = 2,         /* Eo = g (rho_L - rho_G) L_g^2 / sigma                      */
+  GPE_ST_SIGMA = 3,      /* sigma given in lattice units (field sigma)                */
+  GPE_ST_CAPILLARY = 4   /* U_c = sigma / eta_L: sigma = U_c eta_L                    */
+};
+enum gpe_gravity {
+  GPE_GRAV_G = 0,        /* g = G U_c^2 / L_c (G dimensionless, may be 0)             */
+  GPE_GRAV_FR = 1,       /* |g| = U_c^2 / (Fr^2 L_c) along the direction of G        */
+  GPE_GRAV_EO = 2        /* |g| = Eo sigma / ((rho_L - rho_G) L_g^2) along G          */
+};
+enum gpe_rho_ref_kind {
+  GPE_RHO_REF_ZERO = 0, GPE_RHO_REF_LIQUID = 1, GPE_RHO_REF_GAS = 2,
+  GPE_RHO_REF_VALUE = 3  /* rho_ref = rho_ref_value rho_L                             */
+};
+
 typedef struct gpe_problem {
   int32_t geometry, precision;
   int32_t n[3];
   int32_t bc[6];
   int32_t lattice;
-  int32_t capillary_scale; /* 1: U_c = sigma / eta_L (flows with surface tension)     */
   int32_t ch_transport;    /* gpe_ch_transport, copied to gpe_params                    */
-  double N_L;              /* cells per characteristic length L_c                     */
-  double N_t;              /* steps per characteristic time T_c                       */
-  double r_rho;            /* rho_L / rho_G (rho_L = 1)                                */
-  double r_eta;            /* eta_L / eta_G                                            */
-  double Re;               /* rho_L U_c L_c / eta_L                                    */
-  double We;               /* rho_L U_c^2 L_c / sigma (0: no surface tension); ignored
-                              when capillary_scale = 1 (sigma = U_c eta_L)             */
-  double Pe;               /* U_c L_c^2 / (M sigma_ref), sigma_ref = 1                 */
-  double Cn;               /* W / L_c                                                  */
-  double G[3];             /* body force in units of U_c^2 / L_c                      */
-  int32_t rho_ref_kind;    /* 0: rho_ref = 0, 1: rho_L, 2: rho_G                      */
   int32_t scheme;          /* gpe_scheme flags, copied to gpe_params                    */
+  int32_t time_scale;      /* gpe_time_scale                                           */
+  int32_t visc_group;      /* gpe_visc_group                                           */
+  int32_t st_group;        /* gpe_st_group                                             */
+  int32_t gravity;         /* gpe_gravity                                              */
+  int32_t rho_ref_kind;    /* gpe_rho_ref_kind                                         */
+  int32_t reserved;        /* 0                                                        */
+  double N_L;              /* cells per characteristic length L_c                     */
+  double N_t;              /* steps per T_c (GPE_TIME_NT)                              */
+  double Ma;               /* U_c / c_s (GPE_TIME_MA)                                  */
+  double L_g_factor;       /* L_g / L_c of Oh, Eo, Mo (0 means 1)                      */
+  double r_rho;            /* rho_L / rho_G                                            */
+  double r_eta;            /* eta_L / eta_G                                            */
+  double Re, Oh, Mo;       /* the one visc_group selects                               */
+  double We, Eo, sigma;    /* the one st_group selects; Eo also for GPE_GRAV_EO        */
+  double Pe;               /* U_c L_c^2 / (M sigma_ref); 0: M = 0                      */
+  double Cn;               /* W / L_c                                                  */
+  double G[3];             /* GPE_GRAV_G: body force in U_c^2 / L_c; else direction    */
+  double Fr;               /* U_c / sqrt(|g| L_c) (GPE_GRAV_FR)                        */
+  double rho_ref_value;    /* GPE_RHO_REF_VALUE: rho_ref / rho_L                       */
 } gpe_problem;
 
 /* Diagnostics (FP64 reductions in a fixed order: bitwise reproducible). */
@@ -165,10 +204,18 @@ typedef struct gpe_diag {
 
 typedef struct gpe_state gpe_state;
 
-/* Map the problem statement (Sec. 4 parameter choices: dx = L_c/N_L,
- * dt = T_c/N_t, rho_L = 1, U_c = sigma/eta_L when capillary_scale, W = Cn L_c,
- * M from Pe) to lattice-unit parameters.  init_* fields of *out are zeroed.
- * Returns GPE_OK or GPE_EINVAL. */
+/* Map the problem statement (Sec. 4 parameter choices: dx = L_c / N_L,
+ * dt = T_c / N_t, rho_L = 1, sigma_ref = 1, W = Cn L_c, M = U_c L_c^2 / Pe)
+ * to lattice-unit parameters, in this order: U_c; g when given by G or Fr;
+ * sigma when it does not depend on eta_L; eta_L; sigma = U_c eta_L
+ * (GPE_ST_CAPILLARY); g when given by Eo.  With GPE_ST_CAPILLARY, Oh and Mo
+ * are solved for eta_L in closed form (eta_L = Oh^2 rho_L U_c L_g,
+ * eta_L = Mo rho_L^2 U_c^3 / (g (rho_L - rho_G))).  init_* fields of *out are
+ * zeroed.  Returns GPE_EINVAL for a missing or non-positive group, a
+ * combination that leaves a quantity undetermined (GPE_VISC_CAPILLARY with
+ * GPE_ST_CAPILLARY, Eo used for both sigma and g, Eo or Mo with
+ * rho_L <= rho_G or without gravity) or parameters gpe_init_state would
+ * reject as invalid; GPE_OK otherwise. */
 int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out);
 
 /* Bytes of the caller-owned device workspace needed for *p: every resident

@@ -6,11 +6,14 @@ test-suite, the smoke check and the CPU-baseline leg of the benchmark import
 this module; the GPU package never does.
 
 Parameters are passed as the plain problem dictionary produced by
-``paper_2011_00814_amd.workloads`` (lattice units, dx = 1)::
+``paper_2011_00814_amd.workloads``, in lattice units (dx = 1)::
 
     dim, axisym, n (nx, ny, nz), bc (6 ints), lattice, dt, cs2,
     rho_l, rho_g, eta_l, eta_g, sigma, mob, width, g (3), rho_ref,
     optional: flags (ablation bits), ch_rk (2 or 4)
+
+or as a problem statement in dimensionless groups, which the oracle maps to
+lattice units with its own mapping (oracle/problem.py).
 
 States are dicts of float64 numpy arrays of shape (nz, ny, nx) (nz = 1 in
 2-D) with keys p, u, v, w (3-D only), phi.
@@ -22,6 +25,8 @@ import os
 import subprocess
 
 import numpy as np
+
+from . import problem as _problem
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpe_oracle.c")
@@ -92,6 +97,7 @@ def lib():
 
 
 def _params(prob: dict) -> _Params:
+    prob = _problem.lattice_problem(prob)  # a statement in dimensionless groups: the oracle's own mapping
     P = _Params()
     P.dim = int(prob["dim"])
     P.axisym = int(prob.get("axisym", 0))

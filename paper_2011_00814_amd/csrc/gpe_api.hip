@@ -384,7 +384,8 @@ extern "C" {
 
 int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out) {
   if (!in || !out) return GPE_EINVAL;
-  if (!(in->N_L > 0) || !(in->N_t > 0) || !(in->r_rho > 0) || !(in->r_eta > 0) || !(in->Re > 0))
+  const double N_L = in->N_L;
+  if (!(N_L > 0) || !(in->r_rho > 0) || !(in->r_eta > 0) || !(in->Cn > 0) || !(in->Pe >= 0))
     return GPE_EINVAL;
   std::memset(out, 0, sizeof(*out));
   out->geometry = in->geometry;
@@ -394,22 +395,98 @@ int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out) {
   out->lattice = in->lattice;
   out->ch_transport = in->ch_transport;
   out->scheme = in->scheme;
-  // dx = L_c / N_L = 1, dt = T_c / N_t = 1, U_c = L_c / T_c = N_L / N_t
-  const double Uc = in->N_L / in->N_t;
+  // dx = L_c / N_L = 1 and dt = 1; c_s = dx / (sqrt(3) dt)
   out->dt = 1.0;
-  out->cs2 = 1.0 / 3.0;  // c_s = dx / (sqrt(3) dt)
-  out->rho_l = 1.0;
-  out->rho_g = 1.0 / in->r_rho;
-  out->eta_l = out->rho_l * Uc * in->N_L / in->Re;
-  out->eta_g = out->eta_l / in->r_eta;
-  if (in->capillary_scale)
-    out->sigma = Uc * out->eta_l;  // U_c = sigma / eta_L
-  else
-    out->sigma = in->We > 0 ? out->rho_l * Uc * Uc * in->N_L / in->We : 0.0;
-  out->mobility = in->Pe > 0 ? Uc * in->N_L * in->N_L / in->Pe : 0.0;  // sigma_ref = 1
-  out->width = in->Cn * in->N_L;
-  for (int a = 0; a < 3; ++a) out->g[a] = in->G[a] * Uc * Uc / in->N_L;
-  out->rho_ref = in->rho_ref_kind == 1 ? out->rho_l : (in->rho_ref_kind == 2 ? out->rho_g : 0.0);
+  out->cs2 = 1.0 / 3.0;
+  double Uc;
+  if (in->time_scale == GPE_TIME_NT) {
+    if (!(in->N_t > 0)) return GPE_EINVAL;
+    Uc = N_L / in->N_t;
+  } else if (in->time_scale == GPE_TIME_MA) {
+    if (!(in->Ma > 0)) return GPE_EINVAL;
+    Uc = in->Ma * std::sqrt(out->cs2);
+  } else {
+    return GPE_EINVAL;
+  }
+  const double rho_l = 1.0, rho_g = rho_l / in->r_rho, drho = rho_l - rho_g;
+  out->rho_l = rho_l;
+  out->rho_g = rho_g;
+  const double Lg = N_L * (in->L_g_factor > 0 ? in->L_g_factor : 1.0);
+  // direction and, for G and Fr, magnitude of the body force
+  const double gn = std::sqrt(in->G[0] * in->G[0] + in->G[1] * in->G[1] + in->G[2] * in->G[2]);
+  double gmag = -1.0;  // < 0: not yet known
+  if (in->gravity == GPE_GRAV_G) {
+    gmag = gn * Uc * Uc / N_L;
+  } else if (in->gravity == GPE_GRAV_FR) {
+    if (!(in->Fr > 0) || !(gn > 0)) return GPE_EINVAL;
+    gmag = Uc * Uc / (in->Fr * in->Fr * N_L);
+  } else if (in->gravity == GPE_GRAV_EO) {
+    if (!(in->Eo > 0) || !(gn > 0) || !(drho > 0) || in->st_group == GPE_ST_EO) return GPE_EINVAL;
+  } else {
+    return GPE_EINVAL;
+  }
+  // surface tension when it does not depend on eta_L
+  double sigma = -1.0;
+  switch (in->st_group) {
+    case GPE_ST_NONE: sigma = 0.0; break;
+    case GPE_ST_WE:
+      if (!(in->We > 0)) return GPE_EINVAL;
+      sigma = rho_l * Uc * Uc * N_L / in->We;
+      break;
+    case GPE_ST_EO:
+      if (!(in->Eo > 0) || !(gmag > 0) || !(drho > 0)) return GPE_EINVAL;
+      sigma = gmag * drho * Lg * Lg / in->Eo;
+      break;
+    case GPE_ST_SIGMA:
+      if (!(in->sigma >= 0)) return GPE_EINVAL;
+      sigma = in->sigma;
+      break;
+    case GPE_ST_CAPILLARY: break;  // sigma = U_c eta_L below
+    default: return GPE_EINVAL;
+  }
+  const bool capillary = in->st_group == GPE_ST_CAPILLARY;
+  double eta_l;
+  switch (in->visc_group) {
+    case GPE_VISC_RE:
+      if (!(in->Re > 0)) return GPE_EINVAL;
+      eta_l = rho_l * Uc * N_L / in->Re;
+      break;
+    case GPE_VISC_OH:
+      if (!(in->Oh > 0)) return GPE_EINVAL;
+      // Oh^2 = eta_L^2 / (rho_L sigma L_g); with sigma = U_c eta_L it is linear in eta_L
+      eta_l = capillary ? in->Oh * in->Oh * rho_l * Uc * Lg : in->Oh * std::sqrt(rho_l * sigma * Lg);
+      if (!capillary && !(sigma > 0)) return GPE_EINVAL;
+      break;
+    case GPE_VISC_MO:
+      if (!(in->Mo > 0) || !(gmag > 0) || !(drho > 0)) return GPE_EINVAL;
+      if (capillary) {
+        eta_l = in->Mo * rho_l * rho_l * Uc * Uc * Uc / (gmag * drho);
+      } else {
+        if (!(sigma > 0)) return GPE_EINVAL;
+        eta_l = std::pow(in->Mo * rho_l * rho_l * sigma * sigma * sigma / (gmag * drho), 0.25);
+      }
+      break;
+    case GPE_VISC_CAPILLARY:
+      if (capillary || !(sigma > 0)) return GPE_EINVAL;
+      eta_l = sigma / Uc;
+      break;
+    default: return GPE_EINVAL;
+  }
+  if (capillary) sigma = Uc * eta_l;
+  if (in->gravity == GPE_GRAV_EO) gmag = in->Eo * sigma / (drho * Lg * Lg);
+  out->eta_l = eta_l;
+  out->eta_g = eta_l / in->r_eta;
+  out->sigma = sigma;
+  out->mobility = in->Pe > 0 ? Uc * N_L * N_L / in->Pe : 0.0;  // sigma_ref = 1
+  out->width = in->Cn * N_L;
+  for (int a = 0; a < 3; ++a) out->g[a] = gn > 0 ? gmag * in->G[a] / gn : 0.0;
+  switch (in->rho_ref_kind) {
+    case GPE_RHO_REF_ZERO: out->rho_ref = 0.0; break;
+    case GPE_RHO_REF_LIQUID: out->rho_ref = rho_l; break;
+    case GPE_RHO_REF_GAS: out->rho_ref = rho_g; break;
+    case GPE_RHO_REF_VALUE: out->rho_ref = in->rho_ref_value * rho_l; break;
+    default: return GPE_EINVAL;
+  }
   return validate(out) == GPE_OK ? GPE_OK : GPE_EINVAL;
 }
 

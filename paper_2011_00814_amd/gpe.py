@@ -42,11 +42,21 @@ class gpe_params(ctypes.Structure):
 
 class gpe_problem(ctypes.Structure):
     _fields_ = [
-        ("geometry", i32), ("precision", i32), ("n", i32 * 3), ("bc", i32 * 6),
-        ("lattice", i32), ("capillary_scale", i32), ("ch_transport", i32), ("N_L", f64), ("N_t", f64),
-        ("r_rho", f64), ("r_eta", f64), ("Re", f64), ("We", f64), ("Pe", f64), ("Cn", f64),
-        ("G", f64 * 3), ("rho_ref_kind", i32), ("scheme", i32),
+        ("geometry", i32), ("precision", i32), ("n", i32 * 3), ("bc", i32 * 6), ("lattice", i32),
+        ("ch_transport", i32), ("scheme", i32), ("time_scale", i32), ("visc_group", i32), ("st_group", i32),
+        ("gravity", i32), ("rho_ref_kind", i32), ("reserved", i32),
+        ("N_L", f64), ("N_t", f64), ("Ma", f64), ("L_g_factor", f64), ("r_rho", f64), ("r_eta", f64),
+        ("Re", f64), ("Oh", f64), ("Mo", f64), ("We", f64), ("Eo", f64), ("sigma", f64), ("Pe", f64),
+        ("Cn", f64), ("G", f64 * 3), ("Fr", f64), ("rho_ref_value", f64),
     ]
+
+
+GPE_TIME_NT, GPE_TIME_MA = 0, 1
+VISC_GROUP = {"Re": 0, "Oh": 1, "Mo": 2, "capillary": 3}
+ST_GROUP = {"none": 0, "We": 1, "Eo": 2, "sigma": 3, "capillary": 4}
+GRAVITY = {"G": 0, "Fr": 1, "Eo": 2}
+RHO_REF = {"zero": 0, "liquid": 1, "gas": 2}
+GPE_RHO_REF_VALUE = 3
 
 
 class gpe_diag(ctypes.Structure):
@@ -305,8 +315,66 @@ def gpe_ensemble_destroy(e):
     lib().gpe_ensemble_destroy(e)
 
 
+# ---- problem statement (dimensionless groups) -> lattice-unit dictionary ------
+STRUCTURAL = ("dim", "axisym", "n", "bc", "lattice", "precision", "ch_transport", "scheme",
+              "allow_unstable", "init", "meta")
+
+
+def problem_struct(st: dict) -> gpe_problem:
+    """gpe_problem of a problem statement dictionary (see workloads.py)."""
+    pr = gpe_problem()
+    if st["dim"] == 3:
+        pr.geometry = GPE_GEOM_3D
+    else:
+        pr.geometry = GPE_GEOM_AXISYM if st.get("axisym") else GPE_GEOM_2D
+    pr.precision = GPE_FP32 if st.get("precision", "fp64") == "fp32" else GPE_FP64
+    for a in range(3):
+        pr.n[a] = int(st["n"][a])
+    for q in range(6):
+        pr.bc[q] = int(st["bc"][q])
+    pr.lattice = int(st["lattice"])
+    pr.ch_transport = int(st.get("ch_transport", GPE_CH_CONSERVATIVE))
+    pr.scheme = int(st.get("scheme", GPE_SCHEME_PAPER))
+    if "N_t" in st:
+        pr.time_scale, pr.N_t = GPE_TIME_NT, float(st["N_t"])
+    else:
+        pr.time_scale, pr.Ma = GPE_TIME_MA, float(st["Ma"])
+    pr.visc_group = VISC_GROUP[st["visc"]]
+    pr.st_group = ST_GROUP[st.get("st", "none")]
+    pr.gravity = GRAVITY[st.get("gravity", "G")]
+    ref = st.get("rho_ref", "zero")
+    if isinstance(ref, str):
+        pr.rho_ref_kind = RHO_REF[ref]
+    else:
+        pr.rho_ref_kind, pr.rho_ref_value = GPE_RHO_REF_VALUE, float(ref)
+    pr.N_L = float(st["N_L"])
+    pr.L_g_factor = float(st.get("L_g", 1.0))
+    for key in ("r_rho", "r_eta", "Re", "Oh", "Mo", "We", "Eo", "sigma", "Pe", "Cn", "Fr"):
+        setattr(pr, key, float(st.get(key, 0.0)))
+    for a, x in enumerate(st.get("G", (0.0, 0.0, 0.0))):
+        pr.G[a] = float(x)
+    return pr
+
+
+def lattice_problem(prob: dict) -> dict:
+    """Lattice-unit problem dictionary: a problem statement (it has N_L) is
+    mapped by the library's gpe_params_from_dimensionless; a lattice-unit
+    dictionary is returned as it is."""
+    if "N_L" not in prob:
+        return prob
+    P = gpe_params_from_dimensionless(problem_struct(prob))
+    out = {k: prob[k] for k in STRUCTURAL if k in prob}
+    out.setdefault("axisym", 0)
+    out.update(dt=P.dt, cs2=P.cs2, rho_l=P.rho_l, rho_g=P.rho_g, eta_l=P.eta_l, eta_g=P.eta_g, sigma=P.sigma,
+               mob=P.mobility, width=P.width, g=tuple(P.g), rho_ref=P.rho_ref)
+    return out
+
+
 # ---- problem dictionary -> gpe_params ----------------------------------------
 def params_from_problem(prob: dict) -> gpe_params:
+    """gpe_params of a problem dictionary (a statement in dimensionless
+    groups goes through gpe_params_from_dimensionless first)."""
+    prob = lattice_problem(prob)
     P = gpe_params()
     if prob["dim"] == 3:
         P.geometry = GPE_GEOM_3D
@@ -384,8 +452,8 @@ class Solver(_Grid):
     def __init__(self, prob: dict, state: dict | None = None, device: str = "cuda:0", stream=None):
         import torch
 
-        self.prob = prob
-        self.params = params_from_problem(prob)
+        self.prob = lattice_problem(prob)
+        self.params = params_from_problem(self.prob)
         nbytes = gpe_workspace_bytes(self.params)
         if nbytes == 0:
             raise GpeError(GPE_EINVAL, "gpe_workspace_bytes")
@@ -447,7 +515,7 @@ class Ensemble:
     def __init__(self, probs: list, device: str = "cuda:0", stream=None):
         import torch
 
-        self.probs = list(probs)
+        self.probs = [lattice_problem(p) for p in probs]
         self.params = [params_from_problem(p) for p in self.probs]
         nbytes = gpe_ensemble_workspace_bytes(self.params)
         if nbytes == 0:

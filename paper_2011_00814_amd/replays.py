@@ -58,9 +58,7 @@ def _config2(prec):
 
 def _config3(prec):
     prob, st = W.rising_bubble_3d(precision=prec)
-    D = 32.0
-    g = -prob["g"][2]
-    return prob, st, {"L": D, "U": math.sqrt(g * D), "T": math.sqrt(D / g)}
+    return prob, st, {"L": 32.0, "D": 32.0, "kind": "gravity"}      # U = sqrt(g D), T = sqrt(D / g)
 
 
 CASES = {
@@ -168,6 +166,10 @@ def run(name: str, precision: str = "fp64", t_end: float | None = None, n_out: i
         device: str = "cuda:0") -> dict:
     build, t_def, n_def = CASES[name]
     prob, state, sc = build(precision)
+    # a problem statement in dimensionless groups is mapped to lattice units
+    # by the library (gpe_params_from_dimensionless), as the solver does
+    prob = G.lattice_problem(prob)
+    sc = W.reporting_units(sc, prob)
     t_end = t_def if t_end is None else t_end
     n_out = n_def if n_out is None else n_out
     total = int(round(t_end * sc["T"]))

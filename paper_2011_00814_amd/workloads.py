@@ -7,11 +7,26 @@ problems (Sec. 4: static drop / capillary wave, Rayleigh-Taylor instability,
 rising bubble / drop in 3-D).  Both the GPU path and the CPU oracle consume
 what it produces; it imports neither.
 
-A problem dictionary has the keys::
+A problem dictionary comes in one of two forms:
+
+- lattice units (the benchmark configurations that are specified that way,
+  the ensemble and the synthetic test cases)::
 
     dim, axisym, n=(nx, ny, nz), bc=(x-lo, x-hi, y-lo, y-hi, z-lo, z-hi),
     lattice, dt, cs2, rho_l, rho_g, eta_l, eta_g, sigma, mob, width,
     g=(gx, gy, gz), rho_ref, precision ("fp64" | "fp32")
+
+- a problem statement in the paper's dimensionless groups (its Sec. 4
+  set-ups and the rising bubble of the 3-D configuration): the structural
+  keys (dim, axisym, n, bc, lattice, precision, ...) and N_L, N_t or Ma,
+  r_rho, r_eta, the viscosity group (visc = "Re" | "Oh" | "Mo" | "capillary"),
+  the surface-tension group (st = "none" | "We" | "Eo" | "sigma" |
+  "capillary"), gravity ("G" | "Fr" | "Eo", with G a vector or direction),
+  L_g, Pe, Cn, rho_ref ("zero" | "liquid" | "gas" | value).  This module
+  never converts a statement to lattice units: the solver maps it with the
+  library's gpe_params_from_dimensionless, the CPU reference with its own
+  mapping.  Initial fields are built from the statement (interface width
+  W = Cn N_L).
 
 Boundary codes: 0 periodic, 1 no-slip wall, 2 symmetry plane / axis.
 Arrays are float64 numpy arrays of shape (nz, ny, nx) (nz = 1 in 2-D).
@@ -49,6 +64,35 @@ def base_problem(dim=2, n=(64, 64, 1), bc=(0, 0, 0, 0, 0, 0), **kw) -> dict:
     )
     prob.update(kw)
     return prob
+
+
+def statement(dim=2, n=(64, 64, 1), bc=(0, 0, 0, 0, 0, 0), **kw) -> dict:
+    """A problem statement in dimensionless groups (see the module docstring)."""
+    prob = dict(dim=dim, axisym=0, n=tuple(int(v) for v in n), bc=tuple(bc),
+                lattice=9 if dim == 2 else 15, precision="fp64")
+    prob.update(kw)
+    return prob
+
+
+def is_statement(prob: dict) -> bool:
+    return "N_L" in prob
+
+
+def reporting_units(sc: dict, lat: dict) -> dict:
+    """Complete the units a replay reports in from the lattice-unit
+    parameters `lat` of its problem: kind "gravity" gives U = sqrt(|g| D),
+    T = sqrt(D / |g|) (D = sc["D"]); kind "capillary" gives the
+    capillary-inertial U = sqrt(sigma / (rho_L L)), T = L / U; other
+    scales are returned as they are."""
+    out = dict(sc)
+    kind = out.pop("kind", None)
+    if kind == "gravity":
+        g = math.sqrt(sum(x * x for x in lat["g"]))
+        out["U"], out["T"] = math.sqrt(g * out["D"]), math.sqrt(out["D"] / g)
+    elif kind == "capillary":
+        out["U"] = math.sqrt(lat["sigma"] / (lat["rho_l"] * out["L"]))
+        out["T"] = out["L"] / out["U"]
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -96,21 +140,22 @@ def rayleigh_taylor_2d(nx=256, ny=1024, precision="fp64", amp_frac=0.1, W=2.0):
 
 
 def rising_bubble_3d(nx=128, ny=128, nz=256, R=16.0, zc=48.0, precision="fp32", W=2.0,
-                     mob=0.02):
-    """3-D rising bubble, no-slip walls on all faces: density and viscosity
-    ratio 10, D = 2R = 32, U_c = sqrt(g D) = 0.03, Eotvos 10, Morton 1e-4,
-    W = 2, M = 0.02, rho_ref = rho_L, D3Q15; gas bubble of radius R at
-    (nx/2, ny/2, zc)."""
+                     mob=0.02, Fr=1.0, in_kernel_init=False):
+    """3-D rising bubble, no-slip walls on all faces, as a statement: L_c =
+    D = 2R = 32 cells, U_c = 0.03 (N_t = D / U_c) with U_c = sqrt(g D)
+    (Fr = 1); density and viscosity ratio 10, Eotvos 10, Morton 1e-4 on D,
+    Cn = W / D, Pe = U_c D^2 / mob, rho_ref = rho_L, D3Q15; gas bubble of
+    radius R at (nx/2, ny/2, zc), phi = tanh(2 (r - R) / W) (the in-kernel
+    profile of init kind 2 with in_kernel_init, then no state is built)."""
     D = 2.0 * R
     Uc = 0.03
-    g = Uc * Uc / D
-    drho = 0.9
-    sigma = g * drho * D * D / 10.0
-    eta_l = (1e-4 * sigma ** 3 / (g * drho)) ** 0.25
-    prob = base_problem(
-        dim=3, n=(nx, ny, nz), bc=(WALL,) * 6, rho_l=1.0, rho_g=0.1,
-        eta_l=eta_l, eta_g=eta_l / 10.0, sigma=sigma, mob=mob, width=W,
-        g=(0.0, 0.0, -g), rho_ref=1.0, precision=precision)
+    prob = statement(
+        dim=3, n=(nx, ny, nz), bc=(WALL,) * 6, precision=precision,
+        N_L=D, N_t=D / Uc, r_rho=10.0, r_eta=10.0, visc="Mo", Mo=1e-4, st="Eo", Eo=10.0,
+        gravity="Fr", Fr=Fr, G=(0.0, 0.0, -1.0), Pe=Uc * D * D / mob, Cn=W / D, rho_ref="liquid")
+    if in_kernel_init:
+        prob["init"] = {"kind": 2, "center": (nx / 2, ny / 2, zc), "radius": R, "width": W}
+        return prob, None
     x, y, z = _centres(prob)
     r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - zc) ** 2)
     st = zero_state(prob)
@@ -299,26 +344,25 @@ def rt_multimode(seed, nx=256, ny=1024, factor=1, precision="fp32", modes=6, amp
 # The paper's 3-D drop coalescence (Sec. 4, 3-D coalescence; its timing case)
 # --------------------------------------------------------------------------
 def coalescence_3d(n=120, Oh=0.119, lattice=15, precision="fp64", N_t_per_L=10.0):
-    """One eighth of two equal drops touching: box [0, 3 L_c]^3 of n^3 cells
-    (N_L = n / 3 cells per L_c = drop radius), symmetry planes on all six
-    faces, drop centre (L_c, 0, 0) so that it touches its mirror image at
-    x = 0; r_rho = 50, r_eta = 58.8, Oh = eta_L / sqrt(rho_L sigma L_c) with
-    the capillary velocity U_c = sigma / eta_L (Re = We = 1 / Oh^2),
-    Cn = 0.1, Pe = 8e3, N_t = N_t_per_L * N_L steps per T_c = L_c / U_c
-    (N_t = 400 at N_L = 40), c_s^2 = 1/3, no gravity; phi = -tanh(2 (r - R) / W).
-    The paper's parameters exceed this library's (conservative) RK4 stability
-    estimate by a few per cent, hence allow_unstable.  CH convection in the
-    advective form as printed (ch_transport = 1): with a gas 50 times lighter
-    the conservative form lets phi grow at the grid scale in the bulk gas."""
+    """One eighth of two equal drops touching, as a statement: box
+    [0, 3 L_c]^3 of n^3 cells (N_L = n / 3 cells per L_c = drop radius),
+    symmetry planes on all six faces, drop centre (L_c, 0, 0) so that it
+    touches its mirror image at x = 0; r_rho = 50, r_eta = 58.8,
+    Oh = eta_L / sqrt(rho_L sigma L_c) with the capillary velocity
+    U_c = sigma / eta_L (Re = We = 1 / Oh^2), Cn = 0.1, Pe = 8e3,
+    N_t = N_t_per_L * N_L steps per T_c = L_c / U_c (N_t = 400 at N_L = 40),
+    no gravity; phi = -tanh(2 (r - R) / W) (in-kernel drop, init kind 1).
+    The paper's parameters exceed this library's (conservative) RK4
+    stability estimate by a few per cent, hence allow_unstable.  CH
+    convection in the advective form as printed (ch_transport = 1): with a
+    gas 50 times lighter the conservative form lets phi grow at the grid
+    scale in the bulk gas."""
     NL = n / 3.0
-    Uc = NL / (N_t_per_L * NL)          # L_c / T_c in lattice units (dx = dt = 1)
-    eta_l = Uc * NL * Oh * Oh            # Re = Uc L / eta_L = 1 / Oh^2
-    sigma = Uc * eta_l                   # capillary velocity scale
     W = 0.1 * NL
-    prob = base_problem(
-        dim=3, n=(n, n, n), bc=(SYMMETRY,) * 6, lattice=lattice, rho_l=1.0, rho_g=1.0 / 50.0,
-        eta_l=eta_l, eta_g=eta_l / 58.8, sigma=sigma, mob=Uc * NL * NL / 8e3, width=W,
-        precision=precision, allow_unstable=1, ch_transport=1)
+    prob = statement(
+        dim=3, n=(n, n, n), bc=(SYMMETRY,) * 6, lattice=lattice, precision=precision,
+        N_L=NL, N_t=N_t_per_L * NL, r_rho=50.0, r_eta=58.8, visc="Oh", Oh=Oh, st="capillary",
+        Pe=8e3, Cn=0.1, allow_unstable=1, ch_transport=1)
     prob["init"] = {"kind": 1, "center": (NL, 0.0, 0.0), "radius": NL, "width": W}
     return prob
 
@@ -347,21 +391,17 @@ def capillary_wave(NL=64, Nt=384, Cn=0.0625, Pe=2e4, Re=1000.0, ratio=20.0, prec
     h(y) = 1/2 + A_p cos(k (y + 1/2)), A_p = 0.01, k = 2 pi; Re = 1000,
     r_rho = r_eta = 20 (equal kinematic viscosities), U_c = sigma / eta_L.
     The paper's meshes: N_L = 64, N_t = 384, Cn = 1/16, Pe = 2e4 and the
-    refined N_L = 128, N_t = 1920, Cn = 1/32, Pe = 4e4.  Returns (prob,
+    refined N_L = 128, N_t = 1920, Cn = 1/32, Pe = 4e4.  Returns (statement,
     state, scales) with the wave's A_p and k in lattice units."""
-    Uc = NL / Nt
-    eta_l = Uc * NL / Re
-    sigma = Uc * eta_l
+    prob = statement(dim=2, n=(NL, NL // 2, 1), bc=(WALL, WALL, SYMMETRY, SYMMETRY, 0, 0), precision=precision,
+                     N_L=NL, N_t=Nt, r_rho=ratio, r_eta=ratio, visc="Re", Re=Re, st="capillary", Pe=Pe, Cn=Cn)
     W = Cn * NL
-    prob = base_problem(dim=2, n=(NL, NL // 2, 1), bc=(WALL, WALL, SYMMETRY, SYMMETRY, 0, 0),
-                        rho_l=1.0, rho_g=1.0 / ratio, eta_l=eta_l, eta_g=eta_l / ratio, sigma=sigma,
-                        mob=Uc * NL * NL / Pe, width=W, precision=precision)
     x, y, _ = _centres(prob)
     k = 2.0 * math.pi / NL
     Ap = 0.01 * NL
     st = zero_state(prob)
     st["phi"] = np.tanh(2.0 * (x - (0.5 * NL + Ap * np.cos(k * (y + 0.5 * NL)))) / W)
-    scales = {"L": float(NL), "U": Uc, "T": float(Nt), "A_p": Ap, "k": k, "h_eq": 0.5 * NL}
+    scales = {"L": float(NL), "U": NL / Nt, "T": float(Nt), "A_p": Ap, "k": k, "h_eq": 0.5 * NL}
     return prob, st, scales
 
 
@@ -369,29 +409,21 @@ def falling_drop_axisym(NL=50, precision="fp64", ch_transport=0):
     """Falling drop (Sec. 4): axisymmetric [0, 24 R] x [0, 8 R] (z, r) with
     L_c = R; the axis r = 0 is a symmetry line, the other three sides are
     no-slip walls; r_rho = 1.15, r_eta = 1, Eo = g (rho_L - rho_G) D^2 /
-    sigma = 144, Oh = eta_L / sqrt(rho_L D sigma) = 0.0466 (D = 2R) with
-    U_c = sigma / eta_L; N_t = 80 N_L (c = 80), Cn = 0.06, Pe = 1000; gravity
-    along +z on the drop only (rho_ref = rho_G); drop centred at (2R, 0).
-    Reported in U_c' = sqrt(g D), T_c' = sqrt(D / g)."""
-    Nt = 80.0 * NL
-    Uc = NL / Nt
-    D = 2.0 * NL
-    Oh, Eo, r_rho = 0.0466, 144.0, 1.15
-    eta_l = Oh * Oh * D * Uc          # Oh^2 = eta_L^2 / (D sigma), sigma = U_c eta_L
-    sigma = Uc * eta_l
-    rho_g = 1.0 / r_rho
-    g = Eo * sigma / ((1.0 - rho_g) * D * D)
+    sigma = 144, Oh = eta_L / sqrt(rho_L D sigma) = 0.0466 (both on D = 2R)
+    with U_c = sigma / eta_L; N_t = 80 N_L (c = 80), Cn = 0.06, Pe = 1000;
+    gravity along +z on the drop only (rho_ref = rho_G); drop centred at
+    (2R, 0).  Reported in U_c' = sqrt(g D), T_c' = sqrt(D / g)."""
+    prob = statement(
+        dim=2, n=(int(24 * NL), int(8 * NL), 1), bc=(WALL, WALL, SYMMETRY, WALL, 0, 0), precision=precision,
+        axisym=1, N_L=NL, N_t=80.0 * NL, r_rho=1.15, r_eta=1.0, visc="Oh", Oh=0.0466, st="capillary",
+        gravity="Eo", Eo=144.0, L_g=2.0, G=(1.0, 0.0, 0.0), Pe=1000.0, Cn=0.06, rho_ref="gas",
+        ch_transport=ch_transport)
     W = 0.06 * NL
-    prob = base_problem(
-        dim=2, n=(int(24 * NL), int(8 * NL), 1), bc=(WALL, WALL, SYMMETRY, WALL, 0, 0),
-        rho_l=1.0, rho_g=rho_g, eta_l=eta_l, eta_g=eta_l, sigma=sigma, mob=Uc * NL * NL / 1000.0,
-        width=W, g=(g, 0.0, 0.0), rho_ref=rho_g, precision=precision, ch_transport=ch_transport)
-    prob["axisym"] = 1
     x, y, _ = _centres(prob)
     r = np.sqrt((x - 2.0 * NL) ** 2 + y ** 2)
     st = zero_state(prob)
     st["phi"] = -np.tanh(2.0 * (r - NL) / W)
-    scales = {"L": float(NL), "U": math.sqrt(g * D), "T": math.sqrt(D / g), "D": D}
+    scales = {"L": float(NL), "D": 2.0 * NL, "kind": "gravity"}
     return prob, st, scales
 
 
@@ -403,22 +435,16 @@ def coalescence_axisym(NL=40, Oh=0.119, precision="fp64", N_t=None):
     Oh = 0.3), Cn = 0.1, Pe = 8e3; advective CH transport (light gas).
     Reported in U_ci = sqrt(sigma / (rho_L R)), T_ci = R / U_ci."""
     Nt = float(N_t) if N_t else (50.0 if Oh >= 0.3 else 10.0) * NL
-    Uc = NL / Nt
-    eta_l = Uc * NL * Oh * Oh          # Oh^2 = eta_L / (U_c R) with sigma = U_c eta_L
-    sigma = Uc * eta_l
+    prob = statement(
+        dim=2, n=(int(3 * NL), int(3 * NL), 1), bc=(SYMMETRY,) * 4 + (0, 0), precision=precision, axisym=1,
+        N_L=NL, N_t=Nt, r_rho=50.0, r_eta=58.8, visc="Oh", Oh=Oh, st="capillary", Pe=8e3, Cn=0.1,
+        ch_transport=1)
     W = 0.1 * NL
-    prob = base_problem(
-        dim=2, n=(int(3 * NL), int(3 * NL), 1), bc=(SYMMETRY,) * 4 + (0, 0),
-        rho_l=1.0, rho_g=1.0 / 50.0, eta_l=eta_l, eta_g=eta_l / 58.8, sigma=sigma,
-        mob=Uc * NL * NL / 8e3, width=W, precision=precision, ch_transport=1)
-    prob["axisym"] = 1
     x, y, _ = _centres(prob)
     r = np.sqrt((x - NL) ** 2 + y ** 2)
     st = zero_state(prob)
     st["phi"] = -np.tanh(2.0 * (r - NL) / W)
-    Uci = math.sqrt(sigma / NL)
-    scales = {"L": float(NL), "U": Uci, "T": NL / Uci}
-    return prob, st, scales
+    return prob, st, {"L": float(NL), "kind": "capillary"}
 
 
 def coalescence_3d_replay(NL=40, Oh=0.119, lattice=19, precision="fp64", scheme=0):
@@ -431,12 +457,9 @@ def coalescence_3d_replay(NL=40, Oh=0.119, lattice=19, precision="fp64", scheme=
     c = 50.0 if Oh >= 0.3 else 10.0
     prob = coalescence_3d(n=int(3 * NL), Oh=Oh, lattice=lattice, precision=precision, N_t_per_L=c)
     prob = dict(prob, scheme=scheme)
+    st = coalescence_state(prob)
     prob.pop("init")
-    st = coalescence_state(dict(prob, init={"center": (NL, 0.0, 0.0), "radius": float(NL),
-                                            "width": prob["width"]}))
-    Uci = math.sqrt(prob["sigma"] / NL)
-    scales = {"L": float(NL), "U": Uci, "T": NL / Uci}
-    return prob, st, scales
+    return prob, st, {"L": float(NL), "kind": "capillary"}
 
 
 def rt_paper(NL=256, Re=256.0, precision="fp64", ch_transport=0):
@@ -444,23 +467,18 @@ def rt_paper(NL=256, Re=256.0, precision="fp64", ch_transport=0):
     half [0, 4] x [0, 1/2] of the domain in L_c = L_y = lambda, no-slip walls
     at x = 0 and 4, symmetry at y = 0 and 1/2; At = 0.5 (r_rho = 3); Re = 256
     with r_eta = 3 (r_nu = 1) or Re = 3000 with r_eta = 1; U_c = sqrt(lambda
-    g), N_t = 200 N_L (c = 200), Cn = 1/64, Pe = 8e4, sigma = 0; liquid on the
-    left of x = h(y) = 2 + 0.1 cos(2 pi (y + 1/2)), gravity along +x on the
-    liquid (rho_ref = rho_G).  Reported in L_c, U_c, T_c."""
+    g) (Fr = 1), N_t = 200 N_L (c = 200), Cn = 1/64, Pe = 8e4, sigma = 0;
+    liquid on the left of x = h(y) = 2 + 0.1 cos(2 pi (y + 1/2)), gravity
+    along +x on the liquid (rho_ref = rho_G).  Reported in L_c, U_c, T_c."""
     Nt = 200.0 * NL
-    Uc = NL / Nt
-    g = Uc * Uc / NL
-    r_eta = 3.0 if Re < 1000 else 1.0
-    eta_l = Uc * NL / Re
-    W = NL / 64.0
-    prob = base_problem(
-        dim=2, n=(int(4 * NL), int(NL // 2), 1), bc=(WALL, WALL, SYMMETRY, SYMMETRY, 0, 0),
-        rho_l=1.0, rho_g=1.0 / 3.0, eta_l=eta_l, eta_g=eta_l / r_eta, sigma=0.0,
-        mob=Uc * NL * NL / 8e4, width=W, g=(g, 0.0, 0.0), rho_ref=1.0 / 3.0, precision=precision,
+    prob = statement(
+        dim=2, n=(int(4 * NL), int(NL // 2), 1), bc=(WALL, WALL, SYMMETRY, SYMMETRY, 0, 0), precision=precision,
+        N_L=NL, N_t=Nt, r_rho=3.0, r_eta=3.0 if Re < 1000 else 1.0, visc="Re", Re=Re, st="none",
+        gravity="Fr", Fr=1.0, G=(1.0, 0.0, 0.0), Pe=8e4, Cn=1.0 / 64.0, rho_ref="gas",
         ch_transport=ch_transport)
+    W = NL / 64.0
     x, y, _ = _centres(prob)
     h = (2.0 + 0.1 * np.cos(2.0 * math.pi * (y / NL + 0.5))) * NL
     st = zero_state(prob)
     st["phi"] = -np.tanh(2.0 * (x - h) / W)
-    scales = {"L": float(NL), "U": Uc, "T": Nt}
-    return prob, st, scales
+    return prob, st, {"L": float(NL), "U": NL / Nt, "T": Nt}

@@ -5,12 +5,13 @@ symmetry planes on all faces and the growth of the liquid bridge at x = 0."""
 import numpy as np
 import pytest
 
+from oracle.problem import lattice_problem
 from paper_2011_00814_amd import workloads as W
 
 
 def test_coalescence_parameters_follow_the_dimensionless_groups():
     Oh = 0.119
-    p = W.coalescence_3d(n=120, Oh=Oh)
+    p = lattice_problem(W.coalescence_3d(n=120, Oh=Oh))
     NL, Uc = 40.0, 0.1
     # Oh = eta_L / sqrt(rho_L sigma L_c), capillary velocity sigma / eta_L = U_c
     assert abs(p["eta_l"] / np.sqrt(p["rho_l"] * p["sigma"] * NL) - Oh) < 1e-12

@@ -75,7 +75,7 @@ def _case(name, seed=1, precision="fp64"):
     if name == "rt2d_walls":
         prob["g"] = (0.0, -2e-4, 0.0)
     if name == "bubble3d_walls":
-        prob["g"] = (0.0, 0.0, -2e-4)
+        prob["Fr"] = 0.5  # g = U_c^2 / (Fr^2 D) = 2.6e-4 (sigma and eta_L follow from Eo and Mo)
     st = W.perturbed(prob, st, seed, uamp=2e-3, pamp=2e-4)
     return prob, st
 

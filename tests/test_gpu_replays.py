@@ -179,6 +179,7 @@ def test_capillary_wave_meshes_against_prosperetti(gpe, oracle):
 
     def errors(name, series):
         prob, _, sc = R.CASES[name][0]("fp64")
+        prob = gpe.lattice_problem(prob)  # the parameters the solver ran with
         return [(row["t"], row["h_tilde"] - prosperetti(row["t"] * sc["T"], prob["sigma"], sc["k"],
                                                          prob["rho_l"], prob["rho_g"], prob["eta_l"]))
                 for row in series[1:]]

@@ -41,21 +41,21 @@ def test_exports_every_learn_header_symbol(G):
 def test_struct_sizes_match_header_layout(G):
     # 8-byte aligned layouts with no implicit padding
     assert ctypes.sizeof(G.gpe_params) == 4 * 14 + 8 * 13 + 4 * 2 + 8 * 6
-    assert ctypes.sizeof(G.gpe_problem) == 4 * 14 + 8 * 11 + 4 * 2
+    assert ctypes.sizeof(G.gpe_problem) == 4 * 20 + 8 * 19
     assert ctypes.sizeof(G.gpe_diag) == 8 * 9 + 4 * 2
+
+
+def _base(**kw):
+    st = W.statement(dim=2, n=(64, 32, 1), bc=(1, 1, 2, 2, 0, 0), N_L=64.0, N_t=384.0, r_rho=20.0, r_eta=20.0,
+                     visc="Re", Re=1000.0, st="capillary", Pe=2e4, Cn=0.0625)
+    st.update(kw)
+    return st
 
 
 def test_params_from_dimensionless_capillary_wave(G):
     """The paper's capillary-wave set-up: N_L = 64, N_t = 384, Re = 1000,
     r = 20, Cn = 0.0625, Pe = 2e4, U_c = sigma / eta_L."""
-    pr = G.gpe_problem()
-    pr.geometry, pr.precision = G.GPE_GEOM_2D, G.GPE_FP64
-    pr.n[:] = [64, 32, 1]
-    pr.bc[:] = [1, 1, 2, 2, 0, 0]
-    pr.lattice = 9
-    pr.capillary_scale = 1
-    pr.N_L, pr.N_t, pr.r_rho, pr.r_eta, pr.Re, pr.Pe, pr.Cn = 64, 384, 20, 20, 1000, 2e4, 0.0625
-    P = G.gpe_params_from_dimensionless(pr)
+    P = G.gpe_params_from_dimensionless(G.problem_struct(_base()))
     Uc = 64 / 384
     assert P.dt == 1.0 and abs(P.cs2 - 1 / 3) < 1e-16
     assert abs(P.eta_l - Uc * 64 / 1000) < 1e-15
@@ -64,19 +64,112 @@ def test_params_from_dimensionless_capillary_wave(G):
     assert P.width == 4.0 and abs(P.rho_g - 0.05) < 1e-16 and abs(P.eta_g - P.eta_l / 20) < 1e-16
 
 
-def test_params_from_dimensionless_gravity_and_reference_density(G):
-    pr = G.gpe_problem()
-    pr.geometry, pr.precision = G.GPE_GEOM_2D, G.GPE_FP32
-    pr.n[:] = [256, 1024, 1]
-    pr.bc[:] = [0, 0, 1, 1, 0, 0]
-    pr.lattice = 9
-    pr.N_L, pr.N_t, pr.r_rho, pr.r_eta, pr.Re, pr.Pe, pr.Cn = 256, 5120, 3, 1, 3000, 8e4, 2 / 256
-    pr.G[:] = [0, -1, 0]
-    pr.rho_ref_kind = 2
-    P = G.gpe_params_from_dimensionless(pr)
-    Uc = 256 / 5120
-    assert abs(P.g[1] + Uc * Uc / 256) < 1e-18
-    assert abs(P.rho_ref - 1 / 3) < 1e-16 and P.sigma == 0.0
+# Each alternative of the problem statement against its definition, the
+# group computed back from the lattice parameters (Sec. 4 set-ups).
+ALTERNATIVES = {
+    # Ma instead of N_t: U_c = Ma c_s, c_s^2 = 1/3
+    "Ma": (dict(Ma=0.05, N_t=None), lambda P, U: abs(P.sigma / P.eta_l - 0.05 / 3 ** 0.5) < 1e-16),
+    # Oh on the radius with the capillary velocity (coalescence)
+    "Oh": (dict(visc="Oh", Oh=0.119), lambda P, U: abs(P.eta_l / (P.sigma * 64) ** 0.5 - 0.119) < 1e-13),
+    # Oh and Eo on the diameter, gravity from Eo (falling drop)
+    "Oh_Eo_gravity": (dict(visc="Oh", Oh=0.0466, gravity="Eo", Eo=144.0, L_g=2.0, G=(1.0, 0.0, 0.0), r_rho=1.15),
+                      lambda P, U: abs(P.g[0] * (1 - P.rho_g) * 128 ** 2 / P.sigma - 144) < 1e-9
+                      and abs(P.eta_l / (P.sigma * 128) ** 0.5 - 0.0466) < 1e-13 and P.g[1] == 0.0),
+    # We instead of the capillary velocity
+    "We": (dict(st="We", We=12.5), lambda P, U: abs(U * U * 64 / P.sigma - 12.5) < 1e-12),
+    # sigma in lattice units and eta_L from U_c = sigma / eta_L (static drop)
+    "sigma": (dict(st="sigma", sigma=1e-3, visc="capillary", Ma=0.05, N_t=None),
+              lambda P, U: P.sigma == 1e-3 and abs(P.eta_l - 1e-3 / (0.05 / 3 ** 0.5)) < 1e-16),
+    # Fr: |g| = U_c^2 / (Fr^2 L_c) along the given direction
+    "Fr": (dict(gravity="Fr", Fr=0.5, G=(0.0, -2.0, 0.0)), lambda P, U: abs(P.g[1] + U * U / (0.25 * 64)) < 1e-18),
+    # Eo and Mo with gravity from Fr (rising bubble)
+    "Eo_Mo": (dict(gravity="Fr", Fr=1.0, G=(0.0, -1.0, 0.0), st="Eo", Eo=10.0, visc="Mo", Mo=1e-4, r_rho=10.0),
+              lambda P, U: abs(-P.g[1] * 0.9 * 64 ** 2 / P.sigma - 10) < 1e-12
+              and abs(-P.g[1] * 0.9 * P.eta_l ** 4 / P.sigma ** 3 - 1e-4) < 1e-16),
+    # Mo with the capillary velocity: eta_L = Mo rho_L^2 U_c^3 / (g drho)
+    "Mo_capillary": (dict(gravity="Fr", Fr=1.0, G=(0.0, -1.0, 0.0), visc="Mo", Mo=1e-4, r_rho=10.0),
+                     lambda P, U: abs(-P.g[1] * 0.9 * P.eta_l ** 4 / P.sigma ** 3 - 1e-4) < 1e-16
+                     and abs(P.sigma / P.eta_l - U) < 1e-16),
+    # an arbitrary reference density
+    "rho_ref": (dict(rho_ref=0.37), lambda P, U: P.rho_ref == 0.37),
+    "rho_ref_gas": (dict(rho_ref="gas"), lambda P, U: P.rho_ref == P.rho_g),
+}
+
+
+@pytest.mark.parametrize("name", list(ALTERNATIVES))
+def test_params_from_dimensionless_alternatives(G, name):
+    from oracle.problem import lattice_problem
+
+    kw, check = ALTERNATIVES[name]
+    st = _base(**{k: v for k, v in kw.items() if v is not None})
+    for k, v in kw.items():
+        if v is None:
+            st.pop(k)
+    P = G.gpe_params_from_dimensionless(G.problem_struct(st))
+    U = 64 / 384 if "N_t" in st else 0.05 / 3 ** 0.5
+    assert check(P, U), name
+    # the oracle's own mapping gives the same values
+    ref = lattice_problem(st)
+    got = G.lattice_problem(st)
+    for k in ("dt", "cs2", "rho_l", "rho_g", "eta_l", "eta_g", "sigma", "mob", "width", "rho_ref"):
+        assert abs(got[k] - ref[k]) <= 1e-15 * abs(ref[k]), (name, k, got[k], ref[k])
+    for a in range(3):
+        assert abs(got["g"][a] - ref["g"][a]) <= 1e-15 * abs(ref["g"][a]), (name, a)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(visc="capillary"),                             # sigma and eta_L each defined by the other
+    dict(gravity="Eo", Eo=10.0, st="Eo", G=(1.0, 0.0, 0.0)),  # Eo used for both sigma and g
+    dict(st="Eo", Eo=10.0),                             # Eo without gravity
+    dict(visc="Mo", Mo=1e-4),                           # Mo without gravity
+    dict(gravity="Fr", Fr=1.0, G=(0.0, -1.0, 0.0), visc="Mo", Mo=1e-4, r_rho=1.0),  # Mo with rho_L = rho_G
+    dict(gravity="Fr", Fr=0.0, G=(0.0, -1.0, 0.0)),    # Fr must be positive
+    dict(Re=0.0),
+    dict(Cn=0.0),
+    dict(N_L=0.0),
+])
+def test_params_from_dimensionless_rejects_undetermined(G, kw):
+    st = _base(**kw)
+    with pytest.raises(G.GpeError) as e:
+        G.gpe_params_from_dimensionless(G.problem_struct(st))
+    assert e.value.code == G.GPE_EINVAL
+
+
+STATEMENT_WORKLOADS = {
+    "capillary_wave": lambda: W.capillary_wave()[0],
+    "capillary_wave_fine": lambda: W.capillary_wave(NL=128, Nt=1920, Cn=0.03125, Pe=4e4)[0],
+    "falling_drop": lambda: W.falling_drop_axisym()[0],
+    "coalescence_axisym_oh0.037": lambda: W.coalescence_axisym(Oh=0.037)[0],
+    "coalescence_axisym_oh0.3": lambda: W.coalescence_axisym(Oh=0.3)[0],
+    "coalescence_3d": lambda: W.coalescence_3d(),
+    "coalescence_3d_replay": lambda: W.coalescence_3d_replay(NL=12, Oh=0.3, scheme=1)[0],
+    "rt_re256": lambda: W.rt_paper(Re=256.0)[0],
+    "rt_re3000": lambda: W.rt_paper(Re=3000.0)[0],
+    "rising_bubble": lambda: W.rising_bubble_3d()[0],
+    "rising_bubble_small": lambda: W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0, Fr=0.5)[0],
+}
+
+
+@pytest.mark.parametrize("name", list(STATEMENT_WORKLOADS))
+def test_solver_mapping_equals_oracle_mapping(G, name):
+    """Every workload stated in dimensionless groups reaches the solver
+    through gpe_params_from_dimensionless (gpe.lattice_problem) and the
+    oracle through its own mapping: the lattice parameters agree to
+    round-off (measured: bitwise)."""
+    from oracle.problem import lattice_problem
+
+    st = STATEMENT_WORKLOADS[name]()
+    assert W.is_statement(st)
+    got, ref = G.lattice_problem(st), lattice_problem(st)
+    for k in ("dt", "cs2", "rho_l", "rho_g", "eta_l", "eta_g", "sigma", "mob", "width", "rho_ref"):
+        assert abs(got[k] - ref[k]) <= 1e-15 * abs(ref[k]), (k, got[k], ref[k])
+    for a in range(3):
+        assert abs(got["g"][a] - ref["g"][a]) <= 1e-15 * abs(ref["g"][a])
+    for k in ("dim", "axisym", "n", "bc", "lattice", "precision"):
+        assert got[k] == ref[k]
+    # and the solver's parameter block is built from the mapped values
+    P = G.params_from_problem(got)
+    assert P.eta_l == got["eta_l"] and P.sigma == got["sigma"] and P.mobility == got["mob"]
 
 
 def test_workspace_bytes(G):
@@ -114,7 +207,7 @@ def test_invalid_params_rejected(G, mutate):
 
 @pytest.mark.parametrize("scheme,ok", [(0, True), (1, True), (2, True), (3, True), (4, False), (-1, False)])
 def test_scheme_flags_3d(G, scheme, ok):
-    prob, _ = W.rising_bubble_3d(nx=8, ny=8, nz=8)
+    prob = G.lattice_problem(W.rising_bubble_3d(nx=8, ny=8, nz=8)[0])
     P = G.params_from_problem(dict(prob, scheme=scheme))
     assert (G.gpe_workspace_bytes(P) > 0) == ok
 

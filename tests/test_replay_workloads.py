@@ -1,15 +1,23 @@
-"""The paper's experiment set-ups (Sec. 4) in lattice units reproduce their
-dimensionless groups, and the replay driver's cases are well formed."""
+"""The paper's experiment set-ups (Sec. 4), stated in their dimensionless
+groups and mapped to lattice units by the oracle's own mapping, reproduce
+those groups; the replay driver's cases are well formed."""
 import math
 
 import numpy as np
 import pytest
 
+from oracle.problem import lattice_problem
 from paper_2011_00814_amd import workloads as W
 
 
+def _lattice(built):
+    prob, st, sc = built
+    lat = lattice_problem(prob)
+    return lat, st, W.reporting_units(sc, lat)
+
+
 def test_falling_drop_groups():
-    p, st, sc = W.falling_drop_axisym(NL=50)
+    p, st, sc = _lattice(W.falling_drop_axisym(NL=50))
     NL, D = 50.0, 100.0
     assert p["n"] == (1200, 400, 1) and p["axisym"] == 1
     assert p["bc"][:4] == (W.WALL, W.WALL, W.SYMMETRY, W.WALL)
@@ -29,7 +37,7 @@ def test_falling_drop_groups():
 
 @pytest.mark.parametrize("Oh,Nt", [(0.037, 400), (0.119, 400), (0.3, 2000)])
 def test_coalescence_axisym_groups(Oh, Nt):
-    p, st, sc = W.coalescence_axisym(NL=40, Oh=Oh)
+    p, st, sc = _lattice(W.coalescence_axisym(NL=40, Oh=Oh))
     assert p["n"] == (120, 120, 1) and p["bc"][:4] == (W.SYMMETRY,) * 4 and p["ch_transport"] == 1
     Uc = 40.0 / Nt
     assert abs(p["eta_l"] / math.sqrt(p["sigma"] * 40.0) - Oh) < 1e-12
@@ -42,7 +50,7 @@ def test_coalescence_axisym_groups(Oh, Nt):
 
 @pytest.mark.parametrize("Re,r_eta", [(256.0, 3.0), (3000.0, 1.0)])
 def test_rt_paper_groups(Re, r_eta):
-    p, st, sc = W.rt_paper(NL=256, Re=Re)
+    p, st, sc = _lattice(W.rt_paper(NL=256, Re=Re))
     assert p["n"] == (1024, 128, 1) and p["bc"][:4] == (W.WALL, W.WALL, W.SYMMETRY, W.SYMMETRY)
     Uc = 256.0 / 51200.0
     assert abs(math.sqrt(p["g"][0] * 256.0) - Uc) < 1e-15            # U_c = sqrt(lambda g)
@@ -68,7 +76,7 @@ def test_replay_cases_are_defined():
 
 @pytest.mark.parametrize("Oh,Nt,scheme", [(0.037, 400, 2), (0.119, 400, 0), (0.3, 2000, 1)])
 def test_coalescence_3d_replay_groups(Oh, Nt, scheme):
-    p, st, sc = W.coalescence_3d_replay(NL=12, Oh=Oh, scheme=scheme)
+    p, st, sc = _lattice(W.coalescence_3d_replay(NL=12, Oh=Oh, scheme=scheme))
     NL = 12.0
     assert p["n"] == (36, 36, 36) and p["bc"] == (W.SYMMETRY,) * 6 and p["scheme"] == scheme
     assert abs(p["eta_l"] / math.sqrt(p["sigma"] * NL) - Oh) < 1e-12
@@ -86,3 +94,28 @@ def test_checkerboard_measure():
     assert checkerboard(smooth) < 1e-15               # no i j k term: no response
     assert abs(checkerboard(i * j * k * 1.0) - 1.0 / 8.0) < 1e-15  # third mixed derivative
     assert abs(checkerboard(smooth + 1e-3 * cb) - 1e-3) < 1e-12
+
+
+def test_rising_bubble_groups():
+    """Configuration 3 (3-D rising bubble): D = 32, U_c = sqrt(g D) = 0.03,
+    Eo = 10, Mo = 1e-4, density and viscosity ratio 10, M = 0.02."""
+    p = lattice_problem(W.rising_bubble_3d()[0])
+    D, drho = 32.0, 0.9
+    g = -p["g"][2]
+    assert p["g"][0] == 0.0 and p["g"][1] == 0.0
+    assert abs(math.sqrt(g * D) - 0.03) < 1e-15
+    assert abs(g * drho * D * D / p["sigma"] - 10.0) < 1e-12
+    assert abs(g * drho * p["eta_l"] ** 4 / p["sigma"] ** 3 - 1e-4) < 1e-16
+    assert abs(p["rho_g"] - 0.1) < 1e-16 and abs(p["eta_l"] / p["eta_g"] - 10.0) < 1e-12
+    assert abs(p["mob"] - 0.02) < 1e-15 and p["width"] == 2.0 and p["rho_ref"] == 1.0
+
+
+def test_capillary_wave_groups():
+    """Sec. 4.1 on both meshes: Re 1000 with U_c = sigma / eta_L, r = 20."""
+    for NL, Nt, Cn, Pe in ((64, 384, 1 / 16, 2e4), (128, 1920, 1 / 32, 4e4)):
+        p, st, sc = W.capillary_wave(NL=NL, Nt=Nt, Cn=Cn, Pe=Pe)
+        p = lattice_problem(p)
+        Uc = NL / Nt
+        assert abs(Uc * NL / p["eta_l"] - 1000.0) < 1e-9 and abs(p["sigma"] / p["eta_l"] - Uc) < 1e-15
+        assert abs(1 / p["rho_g"] - 20.0) < 1e-12 and abs(p["eta_l"] / p["eta_g"] - 20.0) < 1e-12
+        assert abs(Uc * NL * NL / p["mob"] - Pe) < 1e-6 * Pe and abs(p["width"] - Cn * NL) < 1e-15
