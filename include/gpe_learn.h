@@ -123,6 +123,33 @@ int gpe_cnn_infer(float* const* d_fields, const float* d_params, const void* d_p
                   int32_t W, const float in_scale[4], const float out_scale[4], float* d_out, void* d_scratch,
                   size_t scratch_bytes, void* stream);
 
+/* Capacity, in floats, of the buffer gpe_cnn_infer_noalloc keeps in device
+ * memory (256 KiB on every GPU the library runs on). */
+#define GPE_CNN_INFER_STATIC_FLOATS 65536
+
+/* Allocation-free variant of gpe_cnn_infer, for callers that cannot allocate
+ * device memory or hand over a scratch buffer: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  The same kernels
+ * and arguments without d_scratch / scratch_bytes; results are bitwise those
+ * of gpe_cnn_infer.  The per-tile partial sums live in a buffer of
+ * GPE_CNN_INFER_STATIC_FLOATS floats that the library holds in the device
+ * memory of each GPU it runs on until the process ends; every entry a call
+ * reads is written by the same call first, so no clearing is needed.
+ *  - Limit: gpe_cnn_infer_scratch_bytes(B, H, W) must not exceed
+ *    GPE_CNN_INFER_STATIC_FLOATS * 4 bytes (one float per 32 x 8 tile and one
+ *    per state, e.g. B = 1000 states of 64 x 256); larger batches return
+ *    GPE_EWORKSPACE and launch nothing.
+ *  - Every call on one GPU shares that GPU's buffer: calls that may overlap
+ *    in time on one GPU (different streams, or threads) race; the caller
+ *    orders them, e.g. on one stream.
+ *  - The first call on a device looks the buffer's address up (no
+ *    allocation, no stream operation).
+ *  - Never calls hipMalloc, hipFree or any allocating routine.
+ * Returns GPE_OK, GPE_EINVAL, GPE_EWORKSPACE or GPE_EHIP. */
+int gpe_cnn_infer_noalloc(float* const* d_fields, const float* d_params, const void* d_params_bf16, int32_t B,
+                          int32_t H, int32_t W, const float in_scale[4], const float out_scale[4], float* d_out,
+                          void* stream);
+
 /* Interface position of B states: per column x the outermost phi = 0
  * crossings, the first sign change scanning down from the top row and up
  * from the bottom row, linearly interpolated between cell centres

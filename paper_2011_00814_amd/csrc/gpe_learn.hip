@@ -20,10 +20,18 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "gpe.h"
 #include "gpe_learn.h"
+
+// Scratch of the allocation-free inference entry point: a file-scope device
+// array, one copy on every GPU the library runs on, alive until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is a stand-in, not a device address): the address of each device's copy
+// is looked up once per device with hipGetSymbolAddress (static_scratch).
+static __device__ __align__(256) float scratch[GPE_CNN_INFER_STATIC_FLOATS];
 
 namespace {
 
@@ -793,6 +801,61 @@ hipError_t backward_t(const TA* wa, const TA* x0, const TA* a1, const TA* a2, co
   return weight_grads<C0, C1, TA>(g1, x0, partial, grads + OFF_W1, grads + OFF_B1, B, H, W, s);
 }
 
+// Fused inference of B states with the per-tile partial sums (and then the
+// per-case sums) in `partial`, which holds infer_scratch_floats(B, H, W)
+// floats; every entry is written before it is read, so it needs no clearing.
+size_t infer_scratch_floats(int B, int H, int W) {
+  return (size_t)B * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH) + B;
+}
+
+int infer_launch(float* const* d_fields, const float* d_params, const void* d_params_bf16, int B, int H, int W,
+                 const float in_scale[4], const float out_scale[4], float* d_out, float* partial, hipStream_t s) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
+  }
+  const int tpc = ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
+  const long ntiles = (long)B * tpc;
+  const unsigned grid = (unsigned)std::min<long>(ntiles, 2L * ncu);
+  hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(kBlock), 0, s, d_fields, d_params,
+                     (const bf16*)d_params_bf16, B, H, W, in_scale[0], in_scale[1], in_scale[2], in_scale[3], d_out,
+                     partial);
+  float* sums = partial + ntiles;
+  hipLaunchKernelGGL(case_sums_kernel, dim3(blocks_for(B)), dim3(kBlock), 0, s, (const float*)partial, B, tpc, sums);
+  hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
+                     out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)sums);
+  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+}
+
+bool infer_args_ok(float* const* d_fields, const float* d_params, const void* d_params_bf16, int B, int H, int W,
+                   const float in_scale[4], const float out_scale[4], const float* d_out) {
+  if (!d_fields || !d_params || !d_params_bf16 || !in_scale || !out_scale || !d_out || !dims_ok(B, H, W))
+    return false;
+  for (int c = 0; c < 4; ++c)
+    if (!(in_scale[c] > 0.f)) return false;
+  return true;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, or nullptr.
+float* static_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -933,38 +996,28 @@ int gpe_cnn_apply(float* const* d_fields, const float* d_out, int32_t B, int32_t
 
 size_t gpe_cnn_infer_scratch_bytes(int32_t B, int32_t H, int32_t W) {
   if (!dims_ok(B, H, W)) return 0;
-  return ((size_t)B * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH) + B) * sizeof(float);
+  return infer_scratch_floats(B, H, W) * sizeof(float);
 }
 
 int gpe_cnn_infer(float* const* d_fields, const float* d_params, const void* d_params_bf16, int32_t B, int32_t H,
                   int32_t W, const float in_scale[4], const float out_scale[4], float* d_out, void* d_scratch,
                   size_t scratch_bytes, void* stream) {
-  if (!d_fields || !d_params || !d_params_bf16 || !in_scale || !out_scale || !d_out || !d_scratch ||
-      !dims_ok(B, H, W))
+  if (!d_scratch || !infer_args_ok(d_fields, d_params, d_params_bf16, B, H, W, in_scale, out_scale, d_out))
     return GPE_EINVAL;
-  for (int c = 0; c < 4; ++c)
-    if (!(in_scale[c] > 0.f)) return GPE_EINVAL;
   if (scratch_bytes < gpe_cnn_infer_scratch_bytes(B, H, W)) return GPE_EINVAL;
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
-      ncu = 256;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  const int tpc = ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
-  const long ntiles = (long)B * tpc;
-  const unsigned grid = (unsigned)std::min<long>(ntiles, 2L * ncu);
-  float* partial = (float*)d_scratch;
-  hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(kBlock), 0, s, d_fields, d_params,
-                     (const bf16*)d_params_bf16, B, H, W, in_scale[0], in_scale[1], in_scale[2], in_scale[3], d_out,
-                     partial);
-  float* sums = partial + ntiles;
-  hipLaunchKernelGGL(case_sums_kernel, dim3(blocks_for(B)), dim3(kBlock), 0, s, (const float*)partial, B, tpc, sums);
-  hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
-                     out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)sums);
-  return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
+  return infer_launch(d_fields, d_params, d_params_bf16, B, H, W, in_scale, out_scale, d_out, (float*)d_scratch,
+                      (hipStream_t)stream);
+}
+
+int gpe_cnn_infer_noalloc(float* const* d_fields, const float* d_params, const void* d_params_bf16, int32_t B,
+                          int32_t H, int32_t W, const float in_scale[4], const float out_scale[4], float* d_out,
+                          void* stream) {
+  if (!infer_args_ok(d_fields, d_params, d_params_bf16, B, H, W, in_scale, out_scale, d_out)) return GPE_EINVAL;
+  if (infer_scratch_floats(B, H, W) > (size_t)GPE_CNN_INFER_STATIC_FLOATS) return GPE_EWORKSPACE;
+  float* ptr = static_scratch();
+  if (!ptr) return GPE_EHIP;
+  return infer_launch(d_fields, d_params, d_params_bf16, B, H, W, in_scale, out_scale, d_out, ptr,
+                      (hipStream_t)stream);
 }
 
 int gpe_interface_position(const float* const* d_phi, int32_t B, int32_t H, int32_t W, float* d_out,

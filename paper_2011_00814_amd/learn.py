@@ -47,6 +47,7 @@ def lib():
             "gpe_interface_position": ([vp, i32, i32, i32, vp, vp], ctypes.c_int),
             "gpe_cnn_infer_scratch_bytes": ([i32, i32, i32], sz),
             "gpe_cnn_infer": ([vp, vp, vp, i32, i32, i32, f4, f4, vp, vp, sz, vp], ctypes.c_int),
+            "gpe_cnn_infer_noalloc": ([vp, vp, vp, i32, i32, i32, f4, f4, vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -132,6 +133,11 @@ def gpe_cnn_infer_scratch_bytes(B: int, H: int, W: int) -> int:
 def gpe_cnn_infer(table, params, params_bf16, B, H, W, in_scale, out_scale, out, scratch, scratch_bytes, stream):
     _check(lib().gpe_cnn_infer(_vp(table), _vp(params), _vp(params_bf16), B, H, W, _f4(in_scale), _f4(out_scale),
                                _vp(out), _vp(scratch), scratch_bytes, _vp(stream)), "gpe_cnn_infer")
+
+
+def gpe_cnn_infer_noalloc(table, params, params_bf16, B, H, W, in_scale, out_scale, out, stream):
+    _check(lib().gpe_cnn_infer_noalloc(_vp(table), _vp(params), _vp(params_bf16), B, H, W, _f4(in_scale),
+                                       _f4(out_scale), _vp(out), _vp(stream)), "gpe_cnn_infer_noalloc")
 
 
 def gpe_interface_position(table, B, H, W, out, stream):

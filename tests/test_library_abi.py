@@ -32,7 +32,7 @@ def test_exports_every_learn_header_symbol(G):
     from paper_2011_00814_amd import learn
 
     names = learn.header_functions()
-    assert len(names) == 15
+    assert len(names) == 16
     L = G.lib()
     for n in names:
         assert hasattr(L, n), n
