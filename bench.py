@@ -253,6 +253,38 @@ def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=4000, neval=50,
     return res
 
 
+def hbm_probe(mib: int = 4096, reps: int = 10, workgroups: int = 0) -> dict:
+    """HBM bandwidth of the library's streaming kernels (gpe_hbm_stream:
+    read-only, write-only and copy with 16-byte accesses) on buffers far
+    larger than the last-level cache, timed with events on the stream the
+    kernels run on.  Bytes counted: read n, write n, copy 2n."""
+    import torch
+
+    from paper_2011_00814_amd import gpe
+
+    nbytes = mib * (1 << 20)
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros_like(a)
+    sid = torch.cuda.current_stream().cuda_stream
+    out = {"buffer_mib": mib, "workgroups": workgroups or "8 per CU"}
+    for name, mode, moved in (("read", gpe.GPE_STREAM_READ, nbytes), ("write", gpe.GPE_STREAM_WRITE, nbytes),
+                              ("copy", gpe.GPE_STREAM_COPY, 2 * nbytes)):
+        for _ in range(3):
+            gpe.gpe_hbm_stream(mode, b.data_ptr(), a.data_ptr(), nbytes, workgroups, sid)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            gpe.gpe_hbm_stream(mode, b.data_ptr(), a.data_ptr(), nbytes, workgroups, sid)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_gbs"] = round(moved / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 20) -> float:
     """Practical HBM bandwidth of a plain device copy (read + write bytes / s)."""
     import torch
@@ -377,6 +409,8 @@ def main():
                     help="--workload learned at the reduced size of the default line's summary")
     ap.add_argument("--coalescence-steps", type=int, default=100,
                     help="steps of the paper's 120^3 coalescence timing case in the default line (0: skip)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="print the HBM streaming probe (read / write / copy) over a sweep of work-group counts")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -413,6 +447,11 @@ def main():
     from paper_2011_00814_amd import gpe
 
     gpe.lib()  # fails loudly if the HIP library is not built
+    if args.stream_probe:
+        ncu = torch.cuda.get_device_properties(0).multi_processor_count
+        for wg in (2 * ncu, 4 * ncu, 8 * ncu, 16 * ncu, 32 * ncu):
+            print(json.dumps({"stream_probe": hbm_probe(workgroups=wg), "cus": ncu}), flush=True)
+        return
     if args.workload == "learned":
         r = learned_bench() if not args.learned_reduced else learned_bench(
             ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8)
@@ -451,6 +490,7 @@ def main():
             "config": {"workload": r["workload"]}, "ensemble": r}), flush=True)
         return
     copy_gbs = copy_bandwidth()
+    probe = hbm_probe()
     prob = problem(args.n, args.precision)
     ncell = args.n ** 3
     r = time_solver(prob, args.steps, args.warmup)
@@ -494,6 +534,8 @@ def main():
             "traffic": traffic,
             "copy_gbs_measured": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+            "stream_probe": probe,
+            "frac_of_stream_copy": round(achieved / probe["copy_gbs"], 4),
             "algorithmic_bytes_per_launch": dom[2],
             "launch_ms": round(dom[1], 5),
         },
@@ -503,6 +545,7 @@ def main():
             "achieved": round(step_gbs, 1),
             "frac": round(step_gbs / HBM_PEAK_GBS, 4),
             "frac_of_copy": round(step_gbs / copy_gbs, 4),
+            "frac_of_stream_copy": round(step_gbs / probe["copy_gbs"], 4),
             "roofline_mlups": round(HBM_PEAK_GBS * 1e9 / (step_bytes / ncell) / 1e6, 1),
         },
         "kernels": [{"name": r[0], "ms": round(r[1], 5), "bytes": r[2],

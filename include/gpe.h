@@ -119,6 +119,11 @@ typedef struct gpe_params {
   double rho_ref;          /* reference density absorbed into the pressure            */
   int32_t init_kind;       /* gpe_init_kind (only when h_phi0 == NULL)                 */
   int32_t scheme;          /* gpe_scheme flags; 0 = the paper's scheme                  */
+  int32_t zchunk;          /* planes per work-group along the marching axis (z in 3-D,
+                              y in 2-D); 0 = chosen by the library.  The work split
+                              never changes the result (bitwise).  Single grids only:
+                              the batched ensemble chooses its own                     */
+  int32_t reserved;        /* 0                                                        */
   double init_center[3];   /* cell-centre coordinates (x_c = i + 1/2)                  */
   double init_radius;
   double init_width;       /* profile width (usually = width)                          */
@@ -359,6 +364,23 @@ gpe_state* gpe_ensemble_case(gpe_ensemble* e, int32_t i);
 /* Free the host-side ensemble handle and its case handles (never the
  * workspace).  NULL is ignored. */
 void gpe_ensemble_destroy(gpe_ensemble* e);
+
+/* ------------------------------------------------------------------------
+ * HBM streaming probe (a measurement aid, not part of the method): the
+ * bandwidth a plain streaming kernel reaches on this device, the practical
+ * ceiling the stencil kernels are compared with.  One launch that streams
+ * `bytes` (a multiple of 16; both pointers 16-byte aligned) with 16-byte
+ * accesses, grid-strided over `workgroups` work-groups of 256 threads
+ * (0: 8 per CU):
+ *  - GPE_STREAM_READ: reads d_src (d_dst, >= 4 bytes, receives nothing: a
+ *    sum is stored only if it equals a value it never takes);
+ *  - GPE_STREAM_WRITE: writes a constant into d_dst;
+ *  - GPE_STREAM_COPY: copies d_src to d_dst (non-overlapping).
+ * Asynchronous on the stream; the caller times it.  Returns GPE_OK,
+ * GPE_EINVAL or GPE_EHIP.
+ * ------------------------------------------------------------------------ */
+enum gpe_stream_mode { GPE_STREAM_READ = 0, GPE_STREAM_WRITE = 1, GPE_STREAM_COPY = 2 };
+int gpe_hbm_stream(int32_t mode, void* d_dst, const void* d_src, size_t bytes, int32_t workgroups, void* stream);
 
 /* Free the host-side handle (never the workspace). NULL is ignored. */
 void gpe_destroy(gpe_state* s);

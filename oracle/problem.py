@@ -33,7 +33,7 @@ from __future__ import annotations
 import math
 
 STRUCTURAL = ("dim", "axisym", "n", "bc", "lattice", "precision", "ch_transport", "scheme",
-              "allow_unstable", "init", "flags", "ch_rk", "meta")
+              "allow_unstable", "init", "flags", "ch_rk", "meta", "zchunk")
 
 
 def is_statement(prob: dict) -> bool:

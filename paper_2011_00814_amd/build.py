@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libgpe.so")
-SOURCES = ["gpe_api.hip", "gpe_flow.hip", "gpe_ch.hip", "gpe_misc.hip", "gpe_ensemble.hip", "gpe_learn.hip"]
+SOURCES = ["gpe_api.hip", "gpe_flow.hip", "gpe_ch.hip", "gpe_misc.hip", "gpe_ensemble.hip", "gpe_learn.hip",
+           "gpe_probe.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -3,6 +3,7 @@
 // replay, diagnostics and field transfer.  Implements include/gpe.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -78,6 +79,7 @@ int validate(const gpe_params* p) {
   if (p->scheme < 0 || p->scheme > (GPE_SCHEME_NO_PAVG | GPE_SCHEME_NO_BULK)) return GPE_EINVAL;
   if (p->scheme != GPE_SCHEME_PAPER && dim != 3) return GPE_EINVAL;
   if (p->init_kind < 0 || p->init_kind > 4) return GPE_EINVAL;
+  if (p->zchunk < 0) return GPE_EINVAL;
   if (p->init_kind == GPE_INIT_ELLIPSE && (!(p->init_radius > 0) || !(std::fabs(p->init_amp) < 1.0)))
     return GPE_EINVAL;
   return GPE_OK;
@@ -180,6 +182,7 @@ struct KernelTimer {
 int zchunk_max(size_t esize) { return esize == 8 ? 128 : 64; }
 
 int flow_zchunk(const gpe_state* s, size_t esize) {
+  if (s->P.zchunk > 0) return std::min(s->P.zchunk, s->grid.n[2]);
   const int zmax = zchunk_max(esize);
   if (s->dim == 3)
     return esize == 8 ? gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, double>::TX, gpe::FlowTile<3, double>::TY,
@@ -191,6 +194,7 @@ int flow_zchunk(const gpe_state* s, size_t esize) {
 }
 
 int ch_zchunk(const gpe_state* s, size_t esize) {
+  if (s->P.zchunk > 0) return std::min(s->P.zchunk, s->grid.n[2]);
   const int zmax = zchunk_max(esize);
   if (s->dim == 3)
     return esize == 8 ? gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, double>::TX, gpe::ChTile<3, double>::TY,

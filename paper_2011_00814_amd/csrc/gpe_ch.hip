@@ -85,6 +85,17 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     T f[NP], x[NP], y[NP], z[NP];
   };
   Staged R;  // the values in flight in the main loop
+  // byte offsets of every load pass within a plane (loop invariant): the
+  // cell value and the X / Y face values of the position
+  uint32_t bo_c[NP], bo_x[NP], bo_y[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const auto q = pm.pos(g, p);
+    const bool ok = pm.ok[p];
+    bo_c[p] = (uint32_t)(ok ? q.oc : 0) * (uint32_t)sizeof(T);
+    bo_x[p] = (uint32_t)(ok ? q.ox : 0) * (uint32_t)sizeof(T);
+    bo_y[p] = (uint32_t)(ok ? q.oy : 0) * (uint32_t)sizeof(T);
+  }
   auto fetch = [&](int kf, int kxy, int kz, Staged& r) {
     const ZMap<T> zf(g, kf), zxy(g, kxy), zz(g, kz);
     const T* __restrict__ bf = A.phi_in + zf.zc;
@@ -93,13 +104,13 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     const T* __restrict__ bz = A.usum[2] + zz.zf;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      const auto q = pm.pos(g, p);
-      const bool ok = pm.ok[p];
-      const int oc = ok ? q.oc : 0;
-      r.f[p] = (kf >= -2) ? at(bf, oc) : T(0);
-      r.x[p] = (kxy >= -2) ? at(bx, ok ? q.ox : 0) : T(0);
-      r.y[p] = (DIM == 3 && kxy >= -2) ? at(by, ok ? q.oy : 0) : T(0);
-      r.z[p] = (kz >= -2) ? at(bz, oc) : T(0);
+      refresh(bo_c[p]);
+      refresh(bo_x[p]);
+      if (DIM == 3) refresh(bo_y[p]);
+      r.f[p] = (kf >= -2) ? at_b(bf, bo_c[p]) : T(0);
+      r.x[p] = (kxy >= -2) ? at_b(bx, bo_x[p]) : T(0);
+      r.y[p] = (DIM == 3 && kxy >= -2) ? at_b(by, bo_y[p]) : T(0);
+      r.z[p] = (kz >= -2) ? at_b(bz, bo_c[p]) : T(0);
     }
   };
   auto commit = [&](int kxy, int kz, int sf, int sz, bool do_f, bool do_xy, bool do_z, const Staged& r) {
@@ -194,11 +205,12 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   T uc_cur[3] = {T(0), T(0), T(0)}, uc_next[3] = {T(0), T(0), T(0)};
   // (unconditional: outside the chunk, or in an inactive lane, it loads a
   // value of the chunk that is never used)
+  uint32_t bo_own = (uint32_t)(active ? ij : 0) * (uint32_t)sizeof(T);
   auto fetch_pt = [&](int k, T& ps, T& ac) {
     const size_t po = (size_t)min(max(k, z0), z1 - 1) * ny * nx;
-    const int o = active ? ij : 0;
-    if (NEED_PHIS) ps = at(A.phis + po, o);
-    if (NEED_ACC) ac = at(A.acc + po, o);
+    refresh(bo_own);
+    if (NEED_PHIS) ps = at_b(A.phis + po, bo_own);
+    if (NEED_ACC) ac = at_b(A.acc + po, bo_own);
   };
 
   // FP64: the values of plane k are stored one iteration later, right after
@@ -213,8 +225,8 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   auto store = [&](int k) {
     if (k >= z0 && active) {
       const size_t po = (size_t)k * ny * nx;
-      at(A.out + po, ij) = pv_out;
-      if (WRITES_ACC) at(A.acc + po, ij) = pv_acc;
+      at_b(A.out + po, bo_own) = pv_out;
+      if (WRITES_ACC) at_b(A.acc + po, bo_own) = pv_acc;
     }
   };
 

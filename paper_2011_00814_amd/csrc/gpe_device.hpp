@@ -156,6 +156,22 @@ __device__ __forceinline__ const T& at(const T* plane, int off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + (uint32_t)off * (uint32_t)sizeof(T));
 }
 
+// Element at a 32-bit byte offset from a work-group-uniform base.  Loop
+// invariant offsets are passed through refresh() once per plane: the empty
+// asm statement makes the value look updated in place, so the compiler can
+// neither hoist a 64-bit zero-extended copy out of the plane loop nor keep
+// a copy, and addresses each access as scalar base + 32-bit vector offset
+// (no 64-bit vector add per access).
+__device__ __forceinline__ void refresh(uint32_t& x) { asm volatile("" : "+v"(x)); }
+template <typename T>
+__device__ __forceinline__ const T& at_b(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ T& at_b(T* base, uint32_t byte_off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 // Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }

@@ -89,6 +89,21 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // the plane's first element instead, and on the outermost row, where p and
   // u are never read, an interior tile loads them from the next row (cache
   // lines fetched anyway) and a boundary tile from the mapped position.
+  // byte offsets of every load pass within a plane (loop invariant):
+  // phi at the cell, p and u_Z at the cell (outermost row: the next row),
+  // u_X and u_Y at their faces
+  uint32_t bo_f[NP], bo_c[NP], bo_x[NP], bo_y[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const auto q = pm.pos(g, p);
+    const bool ok = pm.ok[p];
+    const int oc = ok ? q.oc : 0;
+    const int dq = (DIM == 3 && pm.interior && !pm.inner_row(p)) ? nx : 0;
+    bo_f[p] = (uint32_t)oc * (uint32_t)sizeof(T);
+    bo_c[p] = (uint32_t)(oc + dq) * (uint32_t)sizeof(T);
+    bo_x[p] = (uint32_t)((ok ? q.ox : 0) + dq) * (uint32_t)sizeof(T);
+    bo_y[p] = (uint32_t)((ok ? q.oy : 0) + dq) * (uint32_t)sizeof(T);
+  }
   auto fetch = [&](int k, Staged& r) {
     const ZMap<T> z(g, k);
     const T* __restrict__ bp = A.src[0] + z.zc;
@@ -98,15 +113,15 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     const T* __restrict__ bf = A.phi + z.zc;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      const auto q = pm.pos(g, p);
-      const bool ok = pm.ok[p];
-      const int oc = ok ? q.oc : 0;
-      const int dq = (DIM == 3 && pm.interior && !pm.inner_row(p)) ? nx : 0;
-      r.f[p] = at(bf, oc);
-      r.p[p] = at(bp, oc + dq);
-      r.x[p] = at(bx, (ok ? q.ox : 0) + dq);
-      r.y[p] = (DIM == 3) ? at(by, (ok ? q.oy : 0) + dq) : T(0);
-      r.z[p] = at(bz, oc + dq);
+      refresh(bo_f[p]);
+      refresh(bo_c[p]);
+      refresh(bo_x[p]);
+      if (DIM == 3) refresh(bo_y[p]);
+      r.f[p] = at_b(bf, bo_f[p]);
+      r.p[p] = at_b(bp, bo_c[p]);
+      r.x[p] = at_b(bx, bo_x[p]);
+      r.y[p] = (DIM == 3) ? at_b(by, bo_y[p]) : T(0);
+      r.z[p] = at_b(bz, bo_c[p]);
     }
   };
   auto commit = [&](int s, int k, const Staged& r) {
@@ -255,12 +270,14 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // time level n at the thread's own cell (stages 2 and 3), loaded at the
   // top of the plane's step (before the next plane's loads, so that waiting
   // for it in the update does not also wait for those)
+  uint32_t bo_own = (uint32_t)(active ? ij : 0) * (uint32_t)sizeof(T);
   auto fetch_qn = [&](int k, T* dst) {
+    refresh(bo_own);
     if (STAGE >= 2) {  // an inactive lane loads the plane's first element (unused)
-      const size_t ci = (size_t)k * ny * nx + (active ? ij : 0);
+      const size_t pk = (size_t)k * ny * nx;
 #pragma unroll
       for (int f = 0; f < 4; ++f)
-        if (DIM == 3 || f != 2) dst[f] = (STAGE == 3 ? A.dst[f] : A.qn[f])[ci];
+        if (DIM == 3 || f != 2) dst[f] = at_b((STAGE == 3 ? A.dst[f] : A.qn[f]) + pk, bo_own);
     }
   };
 
@@ -432,7 +449,6 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       // ---- Shu-Osher combination of the stage (increment form) ----
       const bool bX = (i == 0 && g.bc[0] != BC_PERIODIC);
       const bool bY = (DIM == 3) && (j == 0 && g.bc[2] != BC_PERIODIC);
-      const size_t ci = (size_t)k * ny * nx + ij;
       T q[4] = {P0[0], UX0[0], (DIM == 3) ? UY0[0] : T(0), UZ0[0]};
       T L[4] = {Lp, LuX, LuY, LuZ};
       T out[4];
@@ -453,14 +469,15 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       if (bX) out[1] = T(0);
       if (bY) out[2] = T(0);
       if (bZ) out[3] = T(0);
-      A.dst[0][ci] = out[0];
-      A.dst[1][ci] = out[1];
-      if (DIM == 3) A.dst[2][ci] = out[2];
-      A.dst[3][ci] = out[3];
+      const size_t pk = (size_t)k * ny * nx;
+      at_b(A.dst[0] + pk, bo_own) = out[0];
+      at_b(A.dst[1] + pk, bo_own) = out[1];
+      if (DIM == 3) at_b(A.dst[2] + pk, bo_own) = out[2];
+      at_b(A.dst[3] + pk, bo_own) = out[3];
       if (STAGE == 3) {
-        A.usum[0][ci] = old[1] + out[1];
-        if (DIM == 3) A.usum[1][ci] = old[2] + out[2];
-        A.usum[2][ci] = old[3] + out[3];
+        at_b(A.usum[0] + pk, bo_own) = old[1] + out[1];
+        if (DIM == 3) at_b(A.usum[1] + pk, bo_own) = old[2] + out[2];
+        at_b(A.usum[2] + pk, bo_own) = old[3] + out[3];
       }
     }
     mu_prev = L0[S_MU * PLANE];

@@ -35,7 +35,8 @@ class gpe_params(ctypes.Structure):
         ("lattice", i32), ("allow_unstable", i32), ("ch_transport", i32), ("dt", f64), ("cs2", f64),
         ("rho_l", f64), ("rho_g", f64), ("eta_l", f64), ("eta_g", f64),
         ("sigma", f64), ("mobility", f64), ("width", f64), ("g", f64 * 3), ("rho_ref", f64),
-        ("init_kind", i32), ("scheme", i32), ("init_center", f64 * 3), ("init_radius", f64),
+        ("init_kind", i32), ("scheme", i32), ("zchunk", i32), ("reserved", i32), ("init_center", f64 * 3),
+        ("init_radius", f64),
         ("init_width", f64), ("init_amp", f64),
     ]
 
@@ -94,6 +95,8 @@ def lib():
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.gpe_params_from_dimensionless.argtypes = [ctypes.POINTER(gpe_problem), ctypes.POINTER(gpe_params)]
         L.gpe_params_from_dimensionless.restype = ctypes.c_int
+        L.gpe_hbm_stream.argtypes = [ctypes.c_int32, vp, vp, sz, ctypes.c_int32, vp]
+        L.gpe_hbm_stream.restype = ctypes.c_int
         L.gpe_workspace_bytes.argtypes = [ctypes.POINTER(gpe_params)]
         L.gpe_workspace_bytes.restype = sz
         L.gpe_init_state.argtypes = [ctypes.POINTER(gpe_params), vp, sz, vp, vp, vp, ctypes.POINTER(vp)]
@@ -258,6 +261,16 @@ def gpe_kernel_times(h, nsteps: int, maxk: int = 16):
     return [(names[q].decode(), ms[q], nb[q]) for q in range(rc)]
 
 
+GPE_STREAM_READ, GPE_STREAM_WRITE, GPE_STREAM_COPY = 0, 1, 2
+
+
+def gpe_hbm_stream(mode: int, d_dst: int, d_src: int, nbytes: int, workgroups: int, stream: int):
+    rc = lib().gpe_hbm_stream(int(mode), ctypes.c_void_p(d_dst), ctypes.c_void_p(d_src), ctypes.c_size_t(nbytes),
+                              int(workgroups), ctypes.c_void_p(stream))
+    if rc:
+        raise GpeError(rc, "gpe_hbm_stream")
+
+
 def gpe_destroy(h):
     lib().gpe_destroy(h)
 
@@ -317,7 +330,7 @@ def gpe_ensemble_destroy(e):
 
 # ---- problem statement (dimensionless groups) -> lattice-unit dictionary ------
 STRUCTURAL = ("dim", "axisym", "n", "bc", "lattice", "precision", "ch_transport", "scheme",
-              "allow_unstable", "init", "meta")
+              "allow_unstable", "init", "meta", "zchunk")
 
 
 def problem_struct(st: dict) -> gpe_problem:
@@ -389,6 +402,7 @@ def params_from_problem(prob: dict) -> gpe_params:
     P.allow_unstable = int(prob.get("allow_unstable", 0))
     P.ch_transport = int(prob.get("ch_transport", GPE_CH_CONSERVATIVE))
     P.scheme = int(prob.get("scheme", GPE_SCHEME_PAPER))
+    P.zchunk = int(prob.get("zchunk", 0))
     P.dt, P.cs2 = float(prob["dt"]), float(prob["cs2"])
     P.rho_l, P.rho_g = float(prob["rho_l"]), float(prob["rho_g"])
     P.eta_l, P.eta_g = float(prob["eta_l"]), float(prob["eta_g"])

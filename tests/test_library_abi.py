@@ -22,7 +22,7 @@ def G():
 
 def test_exports_every_header_symbol(G):
     names = G.header_functions()
-    assert len(names) == 23
+    assert len(names) == 24
     L = G.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -40,7 +40,7 @@ def test_exports_every_learn_header_symbol(G):
 
 def test_struct_sizes_match_header_layout(G):
     # 8-byte aligned layouts with no implicit padding
-    assert ctypes.sizeof(G.gpe_params) == 4 * 14 + 8 * 13 + 4 * 2 + 8 * 6
+    assert ctypes.sizeof(G.gpe_params) == 4 * 14 + 8 * 13 + 4 * 4 + 8 * 6
     assert ctypes.sizeof(G.gpe_problem) == 4 * 20 + 8 * 19
     assert ctypes.sizeof(G.gpe_diag) == 8 * 9 + 4 * 2
 
@@ -196,6 +196,7 @@ def test_workspace_bytes(G):
     lambda P: setattr(P, "rho_g", 0.0),
     lambda P: setattr(P, "ch_transport", 2),    # only 0 (conservative) and 1 (advective)
     lambda P: setattr(P, "scheme", 1),          # ablation variants are 3-D only
+    lambda P: setattr(P, "zchunk", -1),         # 0 = automatic, else planes per work-group
 ])
 def test_invalid_params_rejected(G, mutate):
     prob, _ = W.static_drop_2d()
