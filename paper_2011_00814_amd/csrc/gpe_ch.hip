@@ -209,8 +209,8 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   auto fetch_pt = [&](int k, T& ps, T& ac) {
     const size_t po = (size_t)min(max(k, z0), z1 - 1) * ny * nx;
     refresh(bo_own);
-    if (NEED_PHIS) ps = at_b(A.phis + po, bo_own);
-    if (NEED_ACC) ac = at_b(A.acc + po, bo_own);
+    if (NEED_PHIS) ps = ld_nt(A.phis + po, bo_own);
+    if (NEED_ACC) ac = ld_nt(A.acc + po, bo_own);
   };
 
   // FP64: the values of plane k are stored one iteration later, right after
@@ -225,8 +225,8 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   auto store = [&](int k) {
     if (k >= z0 && active) {
       const size_t po = (size_t)k * ny * nx;
-      at_b(A.out + po, bo_own) = pv_out;
-      if (WRITES_ACC) at_b(A.acc + po, bo_own) = pv_acc;
+      st_nt(A.out + po, bo_own, pv_out);
+      if (WRITES_ACC) st_nt(A.acc + po, bo_own, pv_acc);
     }
   };
 

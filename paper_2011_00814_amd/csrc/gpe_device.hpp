@@ -172,6 +172,18 @@ __device__ __forceinline__ T& at_b(T* base, uint32_t byte_off) {
   return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
 }
 
+// Streaming accesses for values read or written once per launch (the
+// pointwise stage inputs and every output): non-temporal, so they do not
+// displace the halo lines that neighbouring work-groups re-read from L2.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* base, uint32_t byte_off) {
+  return __builtin_nontemporal_load(&at_b(base, byte_off));
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(T* base, uint32_t byte_off, T v) {
+  __builtin_nontemporal_store(v, &at_b(base, byte_off));
+}
+
 // Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }

@@ -277,7 +277,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       const size_t pk = (size_t)k * ny * nx;
 #pragma unroll
       for (int f = 0; f < 4; ++f)
-        if (DIM == 3 || f != 2) dst[f] = at_b((STAGE == 3 ? A.dst[f] : A.qn[f]) + pk, bo_own);
+        if (DIM == 3 || f != 2) dst[f] = ld_nt((STAGE == 3 ? A.dst[f] : A.qn[f]) + pk, bo_own);
     }
   };
 
@@ -470,14 +470,14 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       if (bY) out[2] = T(0);
       if (bZ) out[3] = T(0);
       const size_t pk = (size_t)k * ny * nx;
-      at_b(A.dst[0] + pk, bo_own) = out[0];
-      at_b(A.dst[1] + pk, bo_own) = out[1];
-      if (DIM == 3) at_b(A.dst[2] + pk, bo_own) = out[2];
-      at_b(A.dst[3] + pk, bo_own) = out[3];
+      st_nt(A.dst[0] + pk, bo_own, out[0]);
+      st_nt(A.dst[1] + pk, bo_own, out[1]);
+      if (DIM == 3) st_nt(A.dst[2] + pk, bo_own, out[2]);
+      st_nt(A.dst[3] + pk, bo_own, out[3]);
       if (STAGE == 3) {
-        at_b(A.usum[0] + pk, bo_own) = old[1] + out[1];
-        if (DIM == 3) at_b(A.usum[1] + pk, bo_own) = old[2] + out[2];
-        at_b(A.usum[2] + pk, bo_own) = old[3] + out[3];
+        st_nt(A.usum[0] + pk, bo_own, old[1] + out[1]);
+        if (DIM == 3) st_nt(A.usum[1] + pk, bo_own, old[2] + out[2]);
+        st_nt(A.usum[2] + pk, bo_own, old[3] + out[3]);
       }
     }
     mu_prev = L0[S_MU * PLANE];
