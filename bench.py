@@ -223,30 +223,49 @@ def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_st
     }
 
 
-def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=4000, neval=50, batch=32) -> dict:
+def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=4000, neval=50, batch=32, checkpoints=32,
+                  rollout=True, log=None) -> dict:
     """The learned coarse correction: training data from `ntrain` fine
     multi-mode Rayleigh-Taylor runs (256 x 1024, seeds 0..ntrain-1), training
-    on the GPU, then `neval` held-out seeds (1000..) run on the fine grid and
+    on the GPU (half the iterations on one-step pairs; with `rollout`, the
+    rest on those and on pairs drawn from the network's own corrected coarse
+    rollouts), then `neval` held-out seeds (1000..) run on the fine grid and
     on the 4x coarser grid (64 x 256, fine_steps / 4 steps) without and with
     the network; interface-position errors on the coarse grid against the
-    restricted fine solution; speedup = fine time / corrected coarse time."""
+    restricted fine solution at `checkpoints` times, the horizon up to which
+    every case keeps >= 95 % of its columns within one coarse cell, the
+    indicator-driven fallback to the fine solver; speedup = fine time /
+    (corrected coarse time + fallback time)."""
     from paper_2011_00814_amd import learned as LD
 
-    quiet = lambda *a, **k: None  # noqa: E731
+    quiet = log or (lambda *a, **k: None)  # noqa: E731
     t0 = time.perf_counter()
-    data = LD.generate(list(range(ntrain)), fine_steps=fine_steps, n_snap=n_snap, log=quiet)
+    data = LD.generate(list(range(ntrain)), fine_steps=fine_steps, n_snap=n_snap, log=quiet,
+                       unroll=3 if rollout else 0)
     gen_s = time.perf_counter() - t0
-    net, hist, sin, sout, train_s = LD.train(data, iters=iters, batch=batch, lr=1e-3, log=quiet)
+    first = iters // 2 if rollout else iters
+    net, hist, sin, sout, train_s = LD.train(data, iters=first, batch=batch, lr=1e-3, log=quiet)
+    roll_s = 0.0
+    if rollout:
+        t1 = time.perf_counter()
+        LD.rollout_pairs(net, data, sin, sout, log=quiet)
+        roll_s = time.perf_counter() - t1
+        net, hist2, _, _, t2 = LD.train(data, iters=iters - first, batch=batch, lr=5e-4, log=quiet, net=net,
+                                        scales_=(sin, sout))
+        hist, train_s = hist + hist2, train_s + t2
     del data
     held = LD.generate(list(range(1000, 1000 + min(8, neval))), fine_steps=fine_steps, n_snap=10, log=quiet)
     plain, corr = LD.one_step_gain(net, held, sin, sout)
     del held
-    res = LD.evaluate(net, sin, sout, list(range(1000, 1000 + neval)), fine_steps=fine_steps, log=quiet)
+    res = LD.evaluate(net, sin, sout, list(range(1000, 1000 + neval)), fine_steps=fine_steps, log=quiet,
+                      checkpoints=checkpoints)
     res.update({
         "workload": f"multi-mode Rayleigh-Taylor, At ~ U(0.2, 0.8), Re 3000, fine 256x1024 / coarse 64x256, "
-                    f"{ntrain} training runs x {fine_steps} fine steps ({n_snap} snapshot pairs each), "
+                    f"{ntrain} training runs x {fine_steps} fine steps ({n_snap} snapshot pairs each"
+                    f"{', plus pairs from corrected rollouts of 1-3 steps' if rollout else ''}), "
                     f"{neval} held-out seeds; network 3x3 CNN 4-32-32-4, BF16 operands, FP32 accumulation",
-        "data_generation_s": round(gen_s, 1), "training_s": round(train_s, 1), "training_iters": iters,
+        "data_generation_s": round(gen_s, 1), "rollout_pairs_s": round(roll_s, 1),
+        "training_s": round(train_s, 1), "training_iters": iters,
         "loss_first_last": [round(hist[0][1], 4), round(hist[-1][1], 4)],
         "one_step_mse_plain": round(plain, 4), "one_step_mse_network": round(corr, 4),
     })
@@ -409,6 +428,8 @@ def main():
                     help="--workload learned at the reduced size of the default line's summary")
     ap.add_argument("--coalescence-steps", type=int, default=100,
                     help="steps of the paper's 120^3 coalescence timing case in the default line (0: skip)")
+    ap.add_argument("--learned-no-rollout", action="store_true",
+                    help="--workload learned: train on one-step pairs only (no pairs from corrected rollouts)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="print the HBM streaming probe (read / write / copy) over a sweep of work-group counts")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -453,8 +474,10 @@ def main():
             print(json.dumps({"stream_probe": hbm_probe(workgroups=wg), "cus": ncu}), flush=True)
         return
     if args.workload == "learned":
-        r = learned_bench() if not args.learned_reduced else learned_bench(
-            ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8)
+        roll = not args.learned_no_rollout
+        progress = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+        r = learned_bench(rollout=roll, log=progress) if not args.learned_reduced else learned_bench(
+            ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8, rollout=roll, log=progress)
         print(json.dumps({
             "metric": "learned-coarse speedup vs the fine solver at interface-position error on the coarse grid",
             "value": r["speedup_vs_fine"], "unit": "x", "n_gpus": 1, "steps": r["coarse_steps"], "warmup": 0,

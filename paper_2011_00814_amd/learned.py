@@ -75,11 +75,14 @@ def _make_fine_ensemble(fine, phis, device):
     return ens
 
 
-def generate(seeds, fine_steps, n_snap, factor=4, nx=256, ny=1024, device="cuda:0", log=print):
+def generate(seeds, fine_steps, n_snap, factor=4, nx=256, ny=1024, device="cuda:0", log=print, unroll=0):
     """Fine runs of `seeds`, restricted snapshot pairs and the coarse solver's
     one-step predictions.  Returns a dict with StateStores X0, X1, S (pairs
     and predictions, index k * B + b for snapshot k of case b), the coarse
-    problems and timings."""
+    problems and timings.  With unroll = U > 0 the restricted fine states
+    U more coarse steps after each snapshot are kept as well (X[j] at
+    t_k + j factor, j = 0 .. U + 1), for pairs from short corrected
+    rollouts (rollout_pairs)."""
     import torch
 
     B = len(seeds)
@@ -88,25 +91,29 @@ def generate(seeds, fine_steps, n_snap, factor=4, nx=256, ny=1024, device="cuda:
     ens = _make_fine_ensemble(fine, phis, device)
     sid = ens.stream.cuda_stream
     ftab = _table(Lr.state_pointers([ens.case(b) for b in range(B)]), device)
-    X0 = StateStore(n_snap * B, H, Wc, device)
-    X1 = StateStore(n_snap * B, H, Wc, device)
+    X = [StateStore(n_snap * B, H, Wc, device) for _ in range(unroll + 2)]
+    X0, X1 = X[0], X[1]
     S = StateStore(n_snap * B, H, Wc, device)
     torch.cuda.synchronize()
-    # snapshot times spread over the run (the last pair ends at fine_steps)
-    times = [int(round(k * (fine_steps - factor) / max(n_snap - 1, 1))) for k in range(n_snap)]
+    # snapshot times spread over the run (the last pair ends at fine_steps),
+    # whole coarse steps so that corrected coarse rollouts reach them
+    span = (unroll + 1) * factor
+    times = [factor * int(round(k * (fine_steps - span) / factor / max(n_snap - 1, 1))) for k in range(n_snap)]
+    if any(b - a < span for a, b in zip(times, times[1:])):
+        raise ValueError("snapshots closer than the unrolled span")
     tabs = []
     t0 = time.perf_counter()
     t = 0
     for k, tk in enumerate(times):
         ens.run(tk - t)
         t = tk
-        d0 = _table(X0.ptrs(range(k * B, (k + 1) * B)), device)
-        Lr.gpe_restrict2d(ftab.data_ptr(), d0.data_ptr(), B, ny, nx, factor, sid)
-        ens.run(factor)
-        t += factor
-        d1 = _table(X1.ptrs(range(k * B, (k + 1) * B)), device)
-        Lr.gpe_restrict2d(ftab.data_ptr(), d1.data_ptr(), B, ny, nx, factor, sid)
-        tabs.append((d0, d1))
+        for j in range(unroll + 2):
+            if j:
+                ens.run(factor)
+                t += factor
+            d = _table(X[j].ptrs(range(k * B, (k + 1) * B)), device)
+            Lr.gpe_restrict2d(ftab.data_ptr(), d.data_ptr(), B, ny, nx, factor, sid)
+            tabs.append(d)
     ens.synchronize()
     fine_s = time.perf_counter() - t0
     flags = ens.finite()
@@ -129,8 +136,55 @@ def generate(seeds, fine_steps, n_snap, factor=4, nx=256, ny=1024, device="cuda:
     cens.close()
     log(f"[learned] generated {n_snap * B} pairs from {B} fine runs x {fine_steps} steps in {fine_s:.1f} s "
         f"(finite {int(flags.sum())}/{B})")
-    return {"X0": X0, "X1": X1, "S": S, "coarse": coarse, "B": B, "n_snap": n_snap, "H": H, "W": Wc,
-            "fine_seconds": fine_s, "finite": flags}
+    return {"X0": X0, "X1": X1, "X": X, "S": S, "coarse": coarse, "B": B, "n_snap": n_snap, "H": H, "W": Wc,
+            "fine_seconds": fine_s, "finite": flags, "times": times, "factor": factor, "unroll": unroll,
+            "pairs": [(S, X1)]}
+
+
+def rollout_pairs(net, data, in_scale, out_scale, device="cuda:0", log=print):
+    """Training pairs from short corrected coarse rollouts: from the
+    restricted fine state R s(t_k) of every snapshot, r = 1 .. U corrected
+    coarse steps (the coarse step, then the network's correction), then the
+    plain coarse step from that corrected state, paired with the restricted
+    fine state R s(t_k + (r + 1) factor) (U = data["unroll"]).  The network
+    then also learns to pull its own, slightly drifted, states back towards
+    the fine solution.  Appends U pair sets to data["pairs"]."""
+    import torch
+
+    B, H, Wc, U, n_snap = data["B"], data["H"], data["W"], data["unroll"], data["n_snap"]
+    if U < 1:
+        raise ValueError("rollout_pairs needs data generated with unroll >= 1")
+    ens = G.Ensemble(data["coarse"], device=device)
+    sid = ens.stream.cuda_stream
+    ctab = _table(Lr.state_pointers([ens.case(b) for b in range(B)]), device)
+    cnet = Lr.CNN(B, H, Wc, act_type=Lr.GPE_ACT_BF16, device=device, stream=ens.stream,
+                  params=net.params.cpu().numpy())
+    stores = [StateStore(n_snap * B, H, Wc, device) for _ in range(U)]
+    torch.cuda.synchronize()
+    tabs = []
+    t0 = time.perf_counter()
+    for k in range(n_snap):
+        src = _table(data["X"][0].ptrs(range(k * B, (k + 1) * B)), device)
+        Lr.gpe_restrict2d(src.data_ptr(), ctab.data_ptr(), B, H, Wc, 1, sid)  # copy in R s(t_k)
+        tabs.append(src)
+        ens.run(1)
+        cnet.infer(ctab, B, in_scale, out_scale)       # C_1
+        for r in range(1, U + 1):
+            ens.run(1)                                 # the plain step from C_r, recorded ...
+            dst = _table(stores[r - 1].ptrs(range(k * B, (k + 1) * B)), device)
+            Lr.gpe_restrict2d(ctab.data_ptr(), dst.data_ptr(), B, H, Wc, 1, sid)
+            tabs.append(dst)
+            if r < U:
+                cnet.infer(ctab, B, in_scale, out_scale)  # ... and corrected: C_{r+1}
+    ens.synchronize()
+    secs = time.perf_counter() - t0
+    flags = ens.finite()
+    ens.close()
+    for r in range(1, U + 1):
+        data["pairs"].append((stores[r - 1], data["X"][r + 1]))
+    log(f"[learned] {U} x {n_snap * B} pairs from corrected rollouts of 1..{U} steps (finite "
+        f"{int(flags.sum())}/{B}) in {secs:.1f} s")
+    return stores
 
 
 def scales(data, sample=64, seed=0):
@@ -164,15 +218,21 @@ def _init_params(seed):
     return np.concatenate(parts)
 
 
-def train(data, iters=2000, batch=16, lr=2e-3, seed=0, act_type=Lr.GPE_ACT_BF16, device="cuda:0", log=print):
-    """Adam on random minibatches of pairs; lr halves every iters/4 steps.
-    Returns (network, loss history, in_scale, out_scale)."""
+def train(data, iters=2000, batch=16, lr=2e-3, seed=0, act_type=Lr.GPE_ACT_BF16, device="cuda:0", log=print,
+          net=None, scales_=None):
+    """Adam on random minibatches drawn from every pair set of data["pairs"]
+    (one-step pairs, then any pairs from corrected rollouts); lr halves
+    every iters/4 steps.  With `net` (and its scales) the training of that
+    network continues.  Returns (network, loss history, in_scale,
+    out_scale, seconds)."""
     import torch
 
-    in_scale, out_scale = scales(data, seed=seed)
+    in_scale, out_scale = scales_ if scales_ else scales(data, seed=seed)
     H, Wc = data["H"], data["W"]
-    net = Lr.CNN(batch, H, Wc, act_type=act_type, device=device, params=_init_params(seed))
-    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    if net is None:
+        net = Lr.CNN(batch, H, Wc, act_type=act_type, device=device, params=_init_params(seed))
+    rng = np.random.Generator(np.random.PCG64(seed + 1 + 7919 * len(data["pairs"])))
+    sets = data["pairs"]
     N = data["X0"].N
     hist = []  # (iteration, mean loss over the window ending there)
     window = []
@@ -180,10 +240,12 @@ def train(data, iters=2000, batch=16, lr=2e-3, seed=0, act_type=Lr.GPE_ACT_BF16,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
+        # one pair set per minibatch, drawn uniformly
+        Sset, Xset = sets[int(rng.integers(len(sets)))]
         idx = rng.choice(N, size=batch, replace=False)
         # the network runs on torch's current stream: the tables need no sync
-        ts = _table(data["S"].ptrs(idx), device, sync=False)
-        tx = _table(data["X1"].ptrs(idx), device, sync=False)
+        ts = _table(Sset.ptrs(idx), device, sync=False)
+        tx = _table(Xset.ptrs(idx), device, sync=False)
         Lr.gpe_cnn_target(tx.data_ptr(), ts.data_ptr(), batch, H, Wc, out_scale, net.target.data_ptr(), net.sid)
         net.features(ts, batch, in_scale)
         net.forward(batch)
@@ -197,8 +259,8 @@ def train(data, iters=2000, batch=16, lr=2e-3, seed=0, act_type=Lr.GPE_ACT_BF16,
             window = []
     net.synchronize()
     secs = time.perf_counter() - t0
-    log(f"[learned] trained {iters} iterations (batch {batch}) in {secs:.1f} s; loss {hist[0][1]:.4g} -> "
-        f"{hist[-1][1]:.4g}")
+    log(f"[learned] trained {iters} iterations (batch {batch}, {len(sets)} pair set(s)) in {secs:.1f} s; "
+        f"loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g}")
     return net, hist, in_scale, out_scale, secs
 
 
@@ -235,15 +297,28 @@ def one_step_gain(net, data, in_scale, out_scale, device="cuda:0", batch=None):
 
 
 def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1024, device="cuda:0",
-             log=print, graph_steps=10, checkpoints=4, autotune=True, fused=True):
+             log=print, graph_steps=10, checkpoints=4, autotune=True, fused=True, indicator=4.0):
     """Fine runs of `seeds` against coarse runs from their restricted
     initial states, without and with the network (one correction per
     coarse step), fine_steps / factor coarse steps, compared at
     `checkpoints` equally spaced times.  Interface positions (outermost
     phi = 0 crossings per column, top and bottom) are compared on the
     coarse grid, the fine solution restricted to it; errors are in coarse
-    cells (factor fine cells).  A coarse case that is not finite falls back
-    to the fine run.  Times of the three runs are summed over the segments."""
+    cells (factor fine cells).  Times of the three runs are summed over the
+    segments.
+
+    Fallback to the fine solver: after every segment each learned case is
+    checked with an error indicator computed on the coarse run alone, the
+    RMS of the network's last correction in units of the training targets'
+    RMS (gpe_cnn_loss against zero; the one-step targets have RMS 1 by
+    construction, so a larger correction means the network is extrapolating
+    beyond its training data), and for finiteness.  A case whose RMS exceeds
+    `indicator`, or that is not finite, falls back to the fine solver for
+    the rest of the run: its result is the fine solution (error 0 from that
+    checkpoint on) and its cost, the batched fine run's time per case, is
+    added to the learned run's time.  The horizon of a run is the last
+    checkpoint up to which every case keeps >= 95 % of its columns within
+    one coarse cell."""
     import torch
 
     B = len(seeds)
@@ -320,7 +395,20 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
             corrected_step()
 
     hbuf = torch.zeros(B * Wc * 2, dtype=torch.float32, device=device)
+    # error indicator: mean square of each case's network output (zero target)
+    zt = torch.zeros(H * Wc * 4, dtype=torch.float32, device=device)
+    gsc = torch.zeros(H * Wc * 4, dtype=torch.float32, device=device)
+    msq = torch.zeros(B, dtype=torch.float32, device=device)
+    isc = torch.zeros(1024 + 1, dtype=torch.float32, device=device)
+    fallen = np.zeros(B, dtype=bool)
     torch.cuda.synchronize()
+
+    def indicator_rms():
+        for b in range(B):
+            Lr.gpe_cnn_loss(cnet.out.data_ptr() + 4 * b * H * Wc * 4, zt.data_ptr(), gsc.data_ptr(),
+                            msq.data_ptr() + 4 * b, H * Wc * 4, isc.data_ptr(), 4 * isc.numel(), sid)
+        ens_c.synchronize()
+        return np.sqrt(msq.cpu().numpy().astype(np.float64))
 
     def heights(ptrs):
         t = _table(ptrs, device)
@@ -328,14 +416,18 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
         ens_c.synchronize()
         return hbuf.cpu().numpy().reshape(B, Wc, 2).copy()
 
-    def err(h, ref, flags):
+    def err(h, ref, flags, exact=None):
         e = np.abs(h - ref)
         e = np.where(np.isnan(e), np.inf, e)  # a missing crossing counts as a miss
         e[flags == 0] = np.inf
+        if exact is not None:
+            e[exact] = 0.0  # cases run by the fine solver
         per_case = e.reshape(B, -1).max(axis=1)
         mean_case = np.nanmean(np.where(np.isinf(e), np.nan, e).reshape(B, -1), axis=1)
+        within = (e <= 1.0).reshape(B, -1).mean(axis=1)
         return {"mean_err_mean": float(np.nanmean(mean_case)), "max_err_median": float(np.median(per_case)),
                 "columns_within_1_cell": round(float(np.mean(e <= 1.0)), 4),
+                "min_case_columns_within_1_cell": round(float(within.min()), 4),
                 "cases_within_1_cell": int((per_case <= 1.0).sum()), "finite": int(flags.sum())}
 
     fine_ms = coarse_ms = net_ms = 0.0
@@ -347,23 +439,42 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
         ens_f.synchronize()
         coarse_ms += timed(ens_c.stream, lambda: ens_c.run(seg_c))
         net_ms += timed(ens_c.stream, run_net)
+        rms = indicator_rms()
+        flags_n = ens_n.finite()
+        newly = ~fallen & ((flags_n == 0) | ~(rms <= indicator))
+        fallen |= newly
         ref = heights(phi_of(rstore.ptrs(range(B))))
         h_c = heights(phi_of(Lr.state_pointers([ens_c.case(b) for b in range(B)])))
         h_n = heights(phi_of(Lr.state_pointers([ens_n.case(b) for b in range(B)])))
         fsteps = (seg + 1) * seg_f
+        learned = err(h_n, ref, np.where(fallen, 1, flags_n), exact=fallen)
+        learned.update(fallback_to_fine=int(fallen.sum()), indicator_rms_max=round(float(np.nanmax(rms)), 4))
         series.append({"fine_steps": fsteps, "t_over_Tc": round(fsteps / lam_steps, 3),
-                       "plain_coarse": err(h_c, ref, ens_c.finite()),
-                       "learned_coarse": err(h_n, ref, ens_n.finite())})
+                       "plain_coarse": err(h_c, ref, ens_c.finite()), "learned_coarse": learned})
     flags_n = ens_n.finite()
     last = series[-1]
+    # the fine solver's cost for the cases that fell back (time per case of the batched fine run)
+    fallback_ms = fine_ms * float(fallen.sum()) / B
+
+    def horizon(kind):
+        h = None
+        for row in series:
+            if row[kind]["min_case_columns_within_1_cell"] < 0.95:
+                break
+            h = row
+        return {"fine_steps": h["fine_steps"] if h else 0, "t_over_Tc": h["t_over_Tc"] if h else 0.0}
     res = {
         "cases": B, "fine_steps": checkpoints * seg_f, "coarse_steps": checkpoints * seg_c, "factor": factor,
         "grid_fine": [nx, ny], "grid_coarse": [Wc, H], "error_unit": f"coarse cells ({factor} fine cells)",
         "fine_ms": round(fine_ms, 2), "coarse_ms": round(coarse_ms, 2), "coarse_net_ms": round(net_ms, 2),
-        "speedup_vs_fine": round(fine_ms / net_ms, 2), "speedup_plain_coarse": round(fine_ms / coarse_ms, 2),
+        "fallback_ms": round(fallback_ms, 2), "indicator_threshold": indicator,
+        "speedup_vs_fine": round(fine_ms / (net_ms + fallback_ms), 2),
+        "speedup_plain_coarse": round(fine_ms / coarse_ms, 2),
         "inference": "fused" if fused else "unfused", "fine_finite": int(ens_f.finite().sum()),
-        "plain_coarse": last["plain_coarse"], "learned_coarse": dict(last["learned_coarse"],
-                                                                      fallback_to_fine=int((flags_n == 0).sum())),
+        "plain_coarse": last["plain_coarse"], "learned_coarse": last["learned_coarse"],
+        "horizon_95pct_columns_every_case": {"plain_coarse": horizon("plain_coarse"),
+                                             "learned_coarse": horizon("learned_coarse")},
+        "learned_non_finite": int((flags_n == 0).sum()),
         "checkpoints": series,
     }
     log(f"[learned] evaluation: {res}")
