@@ -385,6 +385,99 @@ __global__ __launch_bounds__(kBlock) void conv_bwd_w_kernel(const float* __restr
   if ((int)threadIdx.x < CO) out[E + threadIdx.x] = bacc;
 }
 
+// The same weight and bias gradients on the matrix cores for bfloat16
+// activations (BF16 path): an implicit GEMM with M = output channels o
+// (padded to 32), N = 32 consecutive values of k = tap CI + i per tile and
+// the reduction over pixels, one v_mfma_f32_32x32x2f32 per 2 pixels, FP32
+// operands (the output gradient stays FP32; a BF16 activation converts to
+// FP32 exactly) and FP32 accumulation.  Fragment layout (lane l): A[l % 32]
+// [l / 32] = gout[p + l / 32][o = l % 32], B[l / 32][l % 32] = x(p + l / 32,
+// k0 + l % 32), D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] as for the other
+// 32 x 32 instructions.  A block of NW waves owns kPixPerBlockM pixels; wave
+// w takes k-tiles w, w + NW, ...; wave 0 also sums the bias gradient.
+constexpr int kPixPerBlockM = 512;
+
+template <int CI, int CO>
+struct BwdWTiles {
+  static constexpr int K = 9 * CI, NKT = (K + 31) / 32;
+  static constexpr int NW = NKT < 4 ? NKT : (NKT % 3 == 0 ? 3 : 4);  // waves per block
+  static constexpr int TPW = (NKT + NW - 1) / NW;                     // k-tiles per wave
+};
+
+template <int CI, int CO>
+__global__ __launch_bounds__((64 * BwdWTiles<CI, CO>::NW)) void conv_bwd_w_mfma_kernel(
+    const float* __restrict__ gout, const bf16* __restrict__ ain, float* __restrict__ partial, int B, int H, int W) {
+  using Tl = BwdWTiles<CI, CO>;
+  constexpr int K = Tl::K, NKT = Tl::NKT, NW = Tl::NW, TPW = Tl::TPW, E = CO * K;
+  static_assert(CO <= 32, "output channels");
+  const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
+  const int col = lane % 32, half = lane / 32;
+  const long P = (long)B * H * W;
+  const long p0 = (long)blockIdx.x * kPixPerBlockM;
+  const long p1 = p0 + kPixPerBlockM < P ? p0 + kPixPerBlockM : P;
+  // the lane's value of k in each of its tiles: tap and channel
+  int tdy[TPW], tdx[TPW], tch[TPW];
+  bool tok[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int kt = wave + t * NW, k = kt * 32 + col;
+    tok[t] = kt < NKT && k < K;
+    const int tap = tok[t] ? k / CI : 4;
+    tdy[t] = tap / 3 - 1;
+    tdx[t] = tap % 3 - 1;
+    tch[t] = tok[t] ? k % CI : 0;
+  }
+  mfma_f32x16 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+  float bacc = 0.f;
+  // pixel of this lane's half, (b, y, x), advanced by 2 per step
+  long p = p0 + half;
+  int xx = (int)(p % W);
+  long rr = p / W;
+  int yy = (int)(rr % H);
+  long bb = rr / H;
+  for (long pp = p0; pp < p1; pp += 2) {
+    const bool vp = p < p1;
+    const float a = (vp && col < CO) ? gout[p * CO + col] : 0.f;
+    if (wave == 0) bacc += a;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      float b = 0.f;
+      const int y2 = yy + tdy[t];
+      if (vp && tok[t] && y2 >= 0 && y2 < H)
+        b = to_float(ain[((bb * H + y2) * W + wrap(xx + tdx[t], W)) * CI + tch[t]]);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
+    }
+    p += 2;
+    xx += 2;
+    while (xx >= W) {
+      xx -= W;
+      if (++yy == H) {
+        yy = 0;
+        ++bb;
+      }
+    }
+  }
+  float* out = partial + (size_t)blockIdx.x * (E + CO);
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int kt = wave + t * NW, k = kt * 32 + col;
+    if (kt >= NKT || k >= K) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = 8 * (r / 4) + 4 * half + (r % 4);
+      if (o < CO) out[o * K + k] = acc[t][r];
+    }
+  }
+  if (wave == 0) {
+    const float other = __shfl_down(bacc, 32, 64);
+    if (lane < CO) out[E + lane] = bacc + other;
+  }
+}
+
 // grads_w[e] = sum over blocks of partial[blk][e] (blocks in order), and the
 // bias entries likewise
 __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const float* partial, int nblk, int E, int CO,
@@ -768,17 +861,47 @@ hipError_t forward_t(const float* prm, const TA* wa, const TA* x0, TA* a1, TA* a
   return hipGetLastError();
 }
 
+// First pass of a two-level reduction of many blocks' partials: mid[c][e] =
+// the sum of partial[k][e] over the kRedChunk consecutive blocks k of chunk c,
+// in block order (the second pass sums the chunks in order: deterministic).
+constexpr int kRedChunk = 32;
+__global__ __launch_bounds__(kBlock) void reduce_chunks_kernel(const float* partial, int nblk, int EE, float* mid) {
+  const int e = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (e >= EE) return;
+  const int k0 = (int)blockIdx.y * kRedChunk;
+  const int k1 = k0 + kRedChunk < nblk ? k0 + kRedChunk : nblk;
+  float s = 0.f;
+  for (int k = k0; k < k1; ++k) s += partial[(size_t)k * EE + e];
+  mid[(size_t)blockIdx.y * EE + e] = s;
+}
+
 size_t gin_floats(int B, int H, int W) { return (size_t)B * H * W * C2; }
 int wblocks(int B, int H, int W) { return (int)(((long)B * H * W + kPixPerBlockW - 1) / kPixPerBlockW); }
+int wblocks_mfma(int B, int H, int W) { return (int)(((long)B * H * W + kPixPerBlockM - 1) / kPixPerBlockM); }
 
 template <int CI, int CO, typename TA>
 hipError_t weight_grads(const float* g, const TA* ain, float* partial, float* gw, float* gb, int B, int H, int W,
                         hipStream_t s) {
-  const int nb = wblocks(B, H, W);
-  hipLaunchKernelGGL((conv_bwd_w_kernel<CI, CO, TA>), dim3(nb), dim3(kBlock), 0, s, g, ain, partial, B, H, W);
+  int nb;
+  if constexpr (std::is_same<TA, bf16>::value) {  // BF16 activations: on the matrix cores
+    nb = wblocks_mfma(B, H, W);
+    hipLaunchKernelGGL((conv_bwd_w_mfma_kernel<CI, CO>), dim3(nb), dim3(64 * BwdWTiles<CI, CO>::NW), 0, s, g, ain,
+                       partial, B, H, W);
+  } else {
+    nb = wblocks(B, H, W);
+    hipLaunchKernelGGL((conv_bwd_w_kernel<CI, CO, TA>), dim3(nb), dim3(kBlock), 0, s, g, ain, partial, B, H, W);
+  }
   const int E = CO * 9 * CI;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(E + CO)), dim3(kBlock), 0, s, partial, nb, E, CO, gw,
-                     gb);
+  if (nb > 2 * kRedChunk) {  // two passes: chunks of kRedChunk blocks, then the chunks
+    const int nc = (nb + kRedChunk - 1) / kRedChunk;
+    float* mid = partial + (size_t)nb * (E + CO);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(blocks_for(E + CO), nc), dim3(kBlock), 0, s, partial, nb, E + CO,
+                       mid);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(E + CO)), dim3(kBlock), 0, s, mid, nc, E, CO, gw, gb);
+  } else {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(E + CO)), dim3(kBlock), 0, s, partial, nb, E, CO, gw,
+                       gb);
+  }
   return hipGetLastError();
 }
 
@@ -868,7 +991,9 @@ size_t gpe_cnn_act_bytes(int32_t act_type) {
 
 size_t gpe_cnn_scratch_bytes(int32_t B, int32_t H, int32_t W) {
   if (!dims_ok(B, H, W)) return 0;
-  const size_t parts = (size_t)wblocks(B, H, W) * kMaxPartials;
+  // per-block partials, then the chunk sums of the two-level reduction
+  const size_t nb = (size_t)std::max(wblocks(B, H, W), wblocks_mfma(B, H, W));
+  const size_t parts = (nb + (nb + kRedChunk - 1) / kRedChunk) * kMaxPartials;
   const size_t loss_parts = 1024;
   return (2 * gin_floats(B, H, W) + parts + loss_parts) * sizeof(float);
 }
