@@ -272,7 +272,7 @@ def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=4000, neval=50,
     return res
 
 
-def hbm_probe(mib: int = 4096, reps: int = 10, workgroups: int = 0) -> dict:
+def hbm_probe(mib: int = 4096, reps: int = 10, workgroups: int = 0, warm: int = 3) -> dict:
     """HBM bandwidth of the library's streaming kernels (gpe_hbm_stream:
     read-only, write-only and copy with 16-byte accesses) on buffers far
     larger than the last-level cache, timed with events on the stream the
@@ -288,7 +288,7 @@ def hbm_probe(mib: int = 4096, reps: int = 10, workgroups: int = 0) -> dict:
     out = {"buffer_mib": mib, "workgroups": workgroups or "8 per CU"}
     for name, mode, moved in (("read", gpe.GPE_STREAM_READ, nbytes), ("write", gpe.GPE_STREAM_WRITE, nbytes),
                               ("copy", gpe.GPE_STREAM_COPY, 2 * nbytes)):
-        for _ in range(3):
+        for _ in range(warm):
             gpe.gpe_hbm_stream(mode, b.data_ptr(), a.data_ptr(), nbytes, workgroups, sid)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -432,6 +432,11 @@ def main():
                     help="--workload learned: train on one-step pairs only (no pairs from corrected rollouts)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="print the HBM streaming probe (read / write / copy) over a sweep of work-group counts")
+    ap.add_argument("--stream-calib", action="store_true",
+                    help="one launch each of the streaming read / write / copy kernels on 1 GiB buffers "
+                         "(calibration of HBM byte counters under a profiler)")
+    ap.add_argument("--no-stream-probe", action="store_true",
+                    help="leave the streaming probe out of the default line (profiled runs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -468,6 +473,9 @@ def main():
     from paper_2011_00814_amd import gpe
 
     gpe.lib()  # fails loudly if the HIP library is not built
+    if args.stream_calib:
+        print(json.dumps({"stream_calib": hbm_probe(mib=1024, reps=1, warm=0), "bytes": 1 << 30}), flush=True)
+        return
     if args.stream_probe:
         ncu = torch.cuda.get_device_properties(0).multi_processor_count
         for wg in (2 * ncu, 4 * ncu, 8 * ncu, 16 * ncu, 32 * ncu):
@@ -513,7 +521,7 @@ def main():
             "config": {"workload": r["workload"]}, "ensemble": r}), flush=True)
         return
     copy_gbs = copy_bandwidth()
-    probe = hbm_probe()
+    probe = None if args.no_stream_probe else hbm_probe()
     prob = problem(args.n, args.precision)
     ncell = args.n ** 3
     r = time_solver(prob, args.steps, args.warmup)
@@ -558,7 +566,7 @@ def main():
             "copy_gbs_measured": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
             "stream_probe": probe,
-            "frac_of_stream_copy": round(achieved / probe["copy_gbs"], 4),
+            "frac_of_stream_copy": round(achieved / probe["copy_gbs"], 4) if probe else None,
             "algorithmic_bytes_per_launch": dom[2],
             "launch_ms": round(dom[1], 5),
         },
@@ -568,7 +576,7 @@ def main():
             "achieved": round(step_gbs, 1),
             "frac": round(step_gbs / HBM_PEAK_GBS, 4),
             "frac_of_copy": round(step_gbs / copy_gbs, 4),
-            "frac_of_stream_copy": round(step_gbs / probe["copy_gbs"], 4),
+            "frac_of_stream_copy": round(step_gbs / probe["copy_gbs"], 4) if probe else None,
             "roofline_mlups": round(HBM_PEAK_GBS * 1e9 / (step_bytes / ncell) / 1e6, 1),
         },
         "kernels": [{"name": r[0], "ms": round(r[1], 5), "bytes": r[2],
