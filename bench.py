@@ -223,7 +223,7 @@ def ensemble_bench(steps: int, warmup: int, precision: str = "fp32", baseline_st
     }
 
 
-def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=4000, neval=50, batch=32, checkpoints=32,
+def learned_bench(ntrain=200, fine_steps=20000, n_snap=40, iters=12000, neval=50, batch=32, checkpoints=32,
                   rollout=True, log=None) -> dict:
     """The learned coarse correction: training data from `ntrain` fine
     multi-mode Rayleigh-Taylor runs (256 x 1024, seeds 0..ntrain-1), training
@@ -430,6 +430,10 @@ def main():
                     help="steps of the paper's 120^3 coalescence timing case in the default line (0: skip)")
     ap.add_argument("--learned-no-rollout", action="store_true",
                     help="--workload learned: train on one-step pairs only (no pairs from corrected rollouts)")
+    ap.add_argument("--learned-iters", type=int, default=0,
+                    help="--workload learned: training iterations (0: the default of the workload)")
+    ap.add_argument("--learned-checkpoints", type=int, default=0,
+                    help="--workload learned: evaluation times (0: the default of the workload)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="print the HBM streaming probe (read / write / copy) over a sweep of work-group counts")
     ap.add_argument("--stream-calib", action="store_true",
@@ -484,8 +488,14 @@ def main():
     if args.workload == "learned":
         roll = not args.learned_no_rollout
         progress = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-        r = learned_bench(rollout=roll, log=progress) if not args.learned_reduced else learned_bench(
-            ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8, rollout=roll, log=progress)
+        kw = dict(rollout=roll, log=progress)
+        if args.learned_reduced:
+            kw.update(ntrain=32, fine_steps=4000, n_snap=16, iters=800, neval=8)
+        if args.learned_iters > 0:
+            kw["iters"] = args.learned_iters
+        if args.learned_checkpoints > 0:
+            kw["checkpoints"] = args.learned_checkpoints
+        r = learned_bench(**kw)
         print(json.dumps({
             "metric": "learned-coarse speedup vs the fine solver at interface-position error on the coarse grid",
             "value": r["speedup_vs_fine"], "unit": "x", "n_gpus": 1, "steps": r["coarse_steps"], "warmup": 0,

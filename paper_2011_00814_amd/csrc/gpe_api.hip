@@ -339,6 +339,9 @@ FlowArgs<T> flow_args(const gpe_state* s, int st, int zchunk) {
   f.c = make_consts<T>(&s->P, s->dim);
   f.phi = buf<T>(s, B_PHI);
   for (int a = 0; a < 3; ++a) f.usum[a] = buf<T>(s, B_US + a);
+  // mu of the frozen phi lives in CH stage buffer A during the flow step (the
+  // CH sub-step's first stage overwrites that buffer before anything reads it)
+  f.mu = buf<T>(s, B_PHA);
   const int src = st == 1 ? B_Q0 : (st == 2 ? B_Q1 : B_Q2);
   const int dst = st == 1 ? B_Q1 : (st == 2 ? B_Q2 : B_Q0);
   for (int q = 0; q < 4; ++q) {

@@ -63,6 +63,7 @@ struct FlowArgs {
   T* dst[4];        // stage output; in stage 3 also time level n (updated in place)
   const T* phi;     // frozen phase field
   T* usum[3];       // stage 3: u^n + u^{n+1} on each face family
+  T* mu;            // FP64: mu of the frozen phi, written by stage 1 and read by stages 2 and 3
 };
 
 enum ChStage { CH_RK2_1 = 0, CH_RK2_2 = 1, CH_RK4_1 = 2, CH_RK4_2 = 3, CH_RK4_3 = 4, CH_RK4_4 = 5 };

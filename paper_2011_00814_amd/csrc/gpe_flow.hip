@@ -5,8 +5,13 @@
 // along Z through ZC output planes.  Each plane of p, u_X, u_Y, u_Z and phi
 // is staged once from HBM into a 3-plane LDS ring (with the in-plane halo
 // and the boundary ghost rules applied while loading); eta and nu are
-// derived from the frozen phi as the plane is staged; mu and div u of the
-// current plane are formed once in LDS; each thread then evaluates the
+// derived from the frozen phi as the plane is staged; div u and mu of the
+// current plane are formed once in LDS.  mu depends on the frozen phi only:
+// in FP64, stage 1 also stores it and stages 2 and 3 stage the stored field
+// like the others (one plane behind them, which the single LDS plane of mu
+// allows) instead of forming it again (in FP32 that was slower: stage 2 no
+// faster, stage 3 8 % slower at the 128-register limit).  Each thread then
+// evaluates the
 // pressure RHS at its cell and the momentum RHS at the three low faces of
 // its cell, applies the Shu-Osher combination of the stage and writes the
 // result.  Stage 3 updates time level n in place and also writes the face
@@ -80,9 +85,11 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // loaded value before commit(), so the loads stay in flight while the
   // current plane is processed.
   constexpr int NP = PlaneMap<T, DIM, PX, PY, NT>::NPASS;
-  struct Staged {  // one plane's loaded values, per load pass
-    T p[NP], x[NP], y[NP], z[NP], f[NP];
+  struct Staged {  // one plane's loaded values, per load pass (m: mu of the plane below)
+    T p[NP], x[NP], y[NP], z[NP], f[NP], m[NP];
   };
+  constexpr bool MU_STORE = sizeof(T) == 8;  // stage 1 stores mu, stages 2 and 3 read it
+  constexpr bool MU_STORED = MU_STORE && STAGE >= 2;
   Staged R;  // the plane in flight in the main loop
   // Every lane issues every load, so no branch separates the loads from the
   // waits for them: a position outside the mapped halo (never read) loads
@@ -104,13 +111,16 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     bo_x[p] = (uint32_t)((ok ? q.ox : 0) + dq) * (uint32_t)sizeof(T);
     bo_y[p] = (uint32_t)((ok ? q.oy : 0) + dq) * (uint32_t)sizeof(T);
   }
-  auto fetch = [&](int k, Staged& r) {
+  // with_mu: also load mu of plane k - 1 (stages 2 and 3)
+  auto fetch = [&](int k, Staged& r, bool with_mu) {
     const ZMap<T> z(g, k);
     const T* __restrict__ bp = A.src[0] + z.zc;
     const T* __restrict__ bx = A.src[1] + z.zc;
     const T* __restrict__ by = A.src[2] + z.zc;
     const T* __restrict__ bz = A.src[3] + z.zf;
     const T* __restrict__ bf = A.phi + z.zc;
+    const T* __restrict__ bm = A.mu;
+    if (MU_STORED && with_mu) bm += ZMap<T>(g, k - 1).zc;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       refresh(bo_f[p]);
@@ -122,9 +132,10 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       r.x[p] = at_b(bx, bo_x[p]);
       r.y[p] = (DIM == 3) ? at_b(by, bo_y[p]) : T(0);
       r.z[p] = at_b(bz, bo_c[p]);
+      if (MU_STORED && with_mu) r.m[p] = at_b(bm, bo_f[p]);
     }
   };
-  auto commit = [&](int s, int k, const Staged& r) {
+  auto commit = [&](int s, int k, const Staged& r, bool with_mu) {
     const ZMap<T> z(g, k);
     T* const e2 = lds + (k & 1) * PLANE;
 #pragma unroll
@@ -141,6 +152,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       lds[(S_PH + s) * PLANE + lp] = ph;
       e2[S_ET * PLANE + lp] = eta;
       e2[S_NU * PLANE + lp] = eta * recip(rho_of(c, ph));
+      if (MU_STORED && with_mu) lds[S_MU * PLANE + lp] = r.m[p];
     }
   };
 
@@ -244,19 +256,20 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // memory latency, not three.
   {
     Staged W0, W1, W2;
-    fetch(z0 - 2, W0);
-    fetch(z0 - 1, W1);
-    fetch(z0, W2);
-    commit(1, z0 - 2, W0);
-    commit(2, z0 - 1, W1);
-    commit(0, z0, W2);
+    fetch(z0 - 2, W0, false);
+    fetch(z0 - 1, W1, false);
+    fetch(z0, W2, true);  // with mu of plane z0 - 1
+    commit(1, z0 - 2, W0, false);
+    commit(2, z0 - 1, W1, false);
+    commit(0, z0, W2, true);
   }
   __syncthreads();
   edges(z0 - 1, 2, 0, false);  // Z-directed edges between planes z0-1 and z0
   // eta and nu of the own cell on the previous plane (carried from plane to plane)
   T eta_prev = L0[S_ET * PLANE + ((z0 - 1) & 1) * PLANE];
   T nu_prev = L0[S_NU * PLANE + ((z0 - 1) & 1) * PLANE];
-  T mu_prev = mu_at(z0 - 1, L0 + (S_PH + 2) * PLANE, L0 + (S_PH + 1) * PLANE, L0 + (S_PH + 0) * PLANE);
+  T mu_prev = MU_STORED ? L0[S_MU * PLANE]
+                        : mu_at(z0 - 1, L0 + (S_PH + 2) * PLANE, L0 + (S_PH + 1) * PLANE, L0 + (S_PH + 0) * PLANE);
   T dv_prev = div_at(z0 - 1, L0 + (S_UX + 2) * PLANE, L0 + (S_UY + 2) * PLANE, L0 + (S_UZ + 2) * PLANE,
                      L0 + (S_UZ + 0) * PLANE);
   T gx_m = prow(L0 + (S_P + 2) * PLANE, 1, EY), gx_0 = prow(L0 + (S_P + 0) * PLANE, 1, EY);
@@ -265,7 +278,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     gy_m = prow(L0 + (S_P + 2) * PLANE, EY, 1);
     gy_0 = prow(L0 + (S_P + 0) * PLANE, EY, 1);
   }
-  fetch(z0 + 1, R);
+  fetch(z0 + 1, R, true);
 
   // time level n at the thread's own cell (stages 2 and 3), loaded at the
   // top of the plane's step (before the next plane's loads, so that waiting
@@ -287,16 +300,16 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   auto step = [&](auto slots, int k) {
     constexpr int S0 = decltype(slots)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
-    __syncthreads();  // readers of slot SP (plane k-2) are done
-    commit(SP, k + 1, R);
+    __syncthreads();  // readers of slot SP (plane k-2) and of mu (plane k-1) are done
+    commit(SP, k + 1, R, true);  // with mu of plane k
     T qn_cur[4] = {T(0), T(0), T(0), T(0)};
     fetch_qn(k, qn_cur);
     // in flight during this plane's work; the chunk's last plane loads plane
     // k + 1 again (just loaded, unused) so that the loads are unconditional
-    fetch(k + 1 < z1 ? k + 2 : k + 1, R);
+    fetch(k + 1 < z1 ? k + 2 : k + 1, R, true);
     __syncthreads();
 
-    // mu and div u of plane k on [-1, T-1] (LDS positions 1 .. T+1)
+    // div u and mu (unless staged) of plane k on [-1, T-1] (LDS positions 1 .. T+1)
     {
       constexpr int EX_N = TX + 1;
       constexpr int EN = (DIM == 3) ? (TX + 1) * (TY + 1) : TX + 1;
@@ -304,7 +317,8 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
         const int ex = e % EX_N, ey = e / EX_N;
         const int q = ((DIM == 3) ? (ey + 1) * PX : 0) + ex + 1;
         T* b = lds + q;
-        b[S_MU * PLANE] = mu_at(k, b + (S_PH + S0) * PLANE, b + (S_PH + SM) * PLANE, b + (S_PH + SP) * PLANE);
+        if (!MU_STORED)
+          b[S_MU * PLANE] = mu_at(k, b + (S_PH + S0) * PLANE, b + (S_PH + SM) * PLANE, b + (S_PH + SP) * PLANE);
         b[S_DV * PLANE] = div_at(k, b + (S_UX + S0) * PLANE, b + (S_UY + S0) * PLANE,
                                  b + (S_UZ + S0) * PLANE, b + (S_UZ + SP) * PLANE);
       }
@@ -474,6 +488,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       st_nt(A.dst[1] + pk, bo_own, out[1]);
       if (DIM == 3) st_nt(A.dst[2] + pk, bo_own, out[2]);
       st_nt(A.dst[3] + pk, bo_own, out[3]);
+      if (MU_STORE && STAGE == 1) st_nt(A.mu + pk, bo_own, MU[0]);
       if (STAGE == 3) {
         st_nt(A.usum[0] + pk, bo_own, old[1] + out[1]);
         if (DIM == 3) st_nt(A.usum[1] + pk, bo_own, old[2] + out[2]);
