@@ -383,6 +383,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   auto iter = [&](int k, auto sk) {
     constexpr int SK = decltype(sk)::value;  // slot of plane k
     constexpr int S1 = (SK + 1) % 3, S2 = (SK + 2) % 3;
+    wave_prio<3>();
     commit(k + 1, k + 2, S2, S2, true, true, true, R);
     if (DEFER) store(k - 1);
     fetch_pt(k + 1, phis_next, acc_next);
@@ -391,8 +392,11 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
       const int d = (k + 1 < z1) ? 1 : 0;
       fetch(k + 2 + d, k + 1 + d, k + 2 + d, R);
     }
+    wave_prio<0>();
     __syncthreads();
+    wave_prio<1>();
     derive(k + 1, std::integral_constant<int, S1>{});
+    wave_prio<0>();
     const T phc = L0[(S_PH + SK) * PLANE];
     if (ADV) {
       // face sums of plane k+1 (X / Y single slots, Z ring slots of k+1, k+2)

@@ -185,6 +185,17 @@ __device__ __forceinline__ void st_nt(T* base, uint32_t byte_off, T v) {
   __builtin_nontemporal_store(v, &at_b(base, byte_off));
 }
 
+// Wave priority on its SIMD (0 lowest .. 3).  The stencil kernels raise it
+// while a wave commits a staged plane to LDS and issues the next plane's
+// global loads, keep it at 1 for the LDS-heavy derived fields and drop it to
+// 0 for the arithmetic of the output, so that memory requests leave as early
+// as possible while the other waves of the SIMD compute.  Raising it for the
+// stores as well was slower.
+template <int P>
+__device__ __forceinline__ void wave_prio() {
+  __builtin_amdgcn_s_setprio(P);
+}
+
 // Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }

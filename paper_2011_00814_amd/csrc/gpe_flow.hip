@@ -301,13 +301,16 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     constexpr int S0 = decltype(slots)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     __syncthreads();  // readers of slot SP (plane k-2) and of mu (plane k-1) are done
+    wave_prio<3>();
     commit(SP, k + 1, R, true);  // with mu of plane k
     T qn_cur[4] = {T(0), T(0), T(0), T(0)};
     fetch_qn(k, qn_cur);
     // in flight during this plane's work; the chunk's last plane loads plane
     // k + 1 again (just loaded, unused) so that the loads are unconditional
     fetch(k + 1 < z1 ? k + 2 : k + 1, R, true);
+    wave_prio<0>();
     __syncthreads();
+    wave_prio<1>();
 
     // div u and mu (unless staged) of plane k on [-1, T-1] (LDS positions 1 .. T+1)
     {
@@ -324,6 +327,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       }
     }
     edges(k, S0, SP, true);
+    wave_prio<0>();
     // pressure-average partial sums of plane k+1 (own column)
     const T gx_p = prow(L0 + (S_P + SP) * PLANE, 1, EY);
     T gy_p = T(0);
