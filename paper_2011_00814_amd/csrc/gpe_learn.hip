@@ -597,9 +597,14 @@ __global__ __launch_bounds__(kBlock) void interface_kernel(const float* const* p
 // output for one TW x TH tile of one state per iteration of a persistent
 // work-group, with every activation in LDS: the input on the tile + 3 cells,
 // layer 1 on the tile + 2, layer 2 on the tile + 1, the output on the tile.
-// All three layers run on the matrix cores with the double-K instruction
-// v_mfma_f32_32x32x16_bf16 in the K order tap, then channel (the last
-// layer uses 4 of the 32 output columns).
+// All three layers run on the matrix cores as products W x X (rows: output
+// channels, columns: pixels) in the K order tap, then channel.  The weights
+// are the A operand and stay in registers for the whole kernel (layers 1
+// and 2) or in LDS (layer 3); the activations are the B operand, read from
+// LDS.  Layers 1 and 2 use v_mfma_f32_32x32x16_bf16 (32 output channels x 32
+// pixels); the 4-channel layer 3 uses v_mfma_f32_16x16x32_bf16 (16 rows, 4
+// of them used, x 16 pixels).  A lane's result then holds consecutive output
+// channels of one pixel, written to LDS as packed 8-byte words.
 // Rows outside [0, H) are zero in every layer's input (zero padding in y);
 // x is periodic.  A region pixel keeps its 32 channels at a 72-byte stride
 // (36 bf16) so that the 32 lanes of a half-wave reading 8 bytes at
@@ -609,45 +614,111 @@ constexpr int kR0W = kTW + 6, kR0H = kTH + 6, kR0N = kR0W * kR0H;
 constexpr int kR1W = kTW + 4, kR1H = kTH + 4, kR1N = kR1W * kR1H;
 constexpr int kR2W = kTW + 2, kR2H = kTH + 2, kR2N = kR2W * kR2H;
 constexpr int kAS = 36;  // bf16 slots per pixel of a 32-channel region
+constexpr int kN1 = (kR1N + 31) / 32, kN2 = (kR2N + 31) / 32;  // 32-pixel column blocks of layers 1 and 2
+
+typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
 
 // round to nearest even in one instruction (v_cvt_pk_bf16_f32); equal to
 // store(bf16&, float) except for the payload of a NaN
 __device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// two values rounded and packed by one v_cvt_pk_bf16_f32 (lo in the low half)
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+  const f32x2_t f = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
+}
 
 __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const* __restrict__ fields,
                                                              const float* __restrict__ prm,
                                                              const bf16* __restrict__ wa, int B, int H, int W,
                                                              float s0, float s1, float s2, float s3,
                                                              float* __restrict__ out, float* __restrict__ partial) {
-  __shared__ uint16_t a1[kR1N * kAS];
-  __shared__ uint16_t a2x[kR2N * kAS];  // the input region (4 channels) until layer 1 is done, then layer 2
-  __shared__ uint2 w1s[12 * 32];        // [tap (9-11 zero)][output]: 4 input channels
-  __shared__ uint2 w2s[72 * 32];        // [K chunk][output]
-  __shared__ uint2 w3s[72 * 4];
-  __shared__ float bs[68];              // b1, b2, b3
+  __shared__ __align__(16) uint16_t a1[kR1N * kAS];
+  __shared__ __align__(16) uint16_t a2x[kR2N * kAS];  // the input region (4 channels) until layer 1 is done, then layer 2
+  __shared__ uint4 w3s[9 * 64];         // layer-3 A operand per K step and lane (rows 4-15 zero)
+  __shared__ float4 bls[16];            // biases of layers 1 and 2, four channels per entry
   __shared__ float red[kBlock / 64];
   static_assert(kR0N * 4 <= kR2N * kAS, "input region fits the layer-2 buffer");
 
-  // weights and biases once per work-group
-  auto pack = [&](const bf16* src) -> uint2 {
-    uint2 v;
+  const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
+  const int kg = lane / 32, col = lane % 32;  // 32 x 32 x 16 fragments
+  const int q16 = lane / 16, c16 = lane % 16;  // 16 x 16 x 32 fragments
+
+  // 8 consecutive bf16 weights as one A fragment (4 words, element 0 low)
+  auto w8 = [&](const bf16* src) -> uint4 {
+    uint4 v;
     v.x = (uint32_t)src[0].bits | ((uint32_t)src[1].bits << 16);
     v.y = (uint32_t)src[2].bits | ((uint32_t)src[3].bits << 16);
+    v.z = (uint32_t)src[4].bits | ((uint32_t)src[5].bits << 16);
+    v.w = (uint32_t)src[6].bits | ((uint32_t)src[7].bits << 16);
     return v;
   };
-  for (int q = threadIdx.x; q < 12 * 32; q += kBlock) {
-    const int tap = q / 32, o = q % 32;
-    w1s[q] = tap < 9 ? pack(wa + OFF_W1 + (size_t)o * 36 + tap * 4) : make_uint2(0u, 0u);
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  // layer 1: K step s holds taps 4 s + 2 kg and 4 s + 2 kg + 1 (4 channels
+  // each) of output channel col; taps 9-11 are zero
+  uint4 w1r[3];
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const int ta = 4 * st + 2 * kg;
+    if (ta + 1 < 9) {
+      w1r[st] = w8(wa + OFF_W1 + (size_t)col * 36 + ta * 4);
+    } else if (ta < 9) {
+      const bf16* src = wa + OFF_W1 + (size_t)col * 36 + ta * 4;
+      w1r[st] = make_uint4((uint32_t)src[0].bits | ((uint32_t)src[1].bits << 16),
+                           (uint32_t)src[2].bits | ((uint32_t)src[3].bits << 16), 0u, 0u);
+    } else {
+      w1r[st] = z4;
+    }
   }
-  for (int q = threadIdx.x; q < 72 * 32; q += kBlock) w2s[q] = pack(wa + OFF_W2 + (size_t)(q % 32) * 288 + (q / 32) * 4);
-  for (int q = threadIdx.x; q < 72 * 4; q += kBlock) w3s[q] = pack(wa + OFF_W3 + (size_t)(q % 4) * 288 + (q / 4) * 4);
-  for (int q = threadIdx.x; q < 68; q += kBlock)
-    bs[q] = q < 32 ? prm[OFF_B1 + q] : (q < 64 ? prm[OFF_B2 + q - 32] : prm[OFF_B3 + q - 64]);
+  // layer 2: K step s holds tap s / 2, channels 16 (s % 2) + 8 kg .. + 7
+  uint4 w2r[18];
+#pragma unroll
+  for (int st = 0; st < 18; ++st) w2r[st] = w8(wa + OFF_W2 + (size_t)col * 288 + 16 * st + 8 * kg);
+  // layer 3 (16 x 16 x 32): K step s is tap s, channels 8 q16 .. + 7 of row c16
+  for (int q = threadIdx.x; q < 9 * 64; q += kBlock) {
+    const int st = q / 64, l = q % 64;
+    w3s[q] = (l % 16) < 4 ? w8(wa + OFF_W3 + (size_t)(l % 16) * 288 + 32 * st + 8 * (l / 16)) : z4;
+  }
+  // biases: layers 1 and 2 in LDS (entry 8 l + c / 4 holds channels c .. c + 3
+  // of layer l + 1), layer 3 in registers (rows 4 q16 + r, those of q16 = 0 used)
+  if (threadIdx.x < 16) {
+    const float* src = prm + (threadIdx.x < 8 ? OFF_B1 : OFF_B2) + 4 * (threadIdx.x % 8);
+    bls[threadIdx.x] = make_float4(src[0], src[1], src[2], src[3]);
+  }
+  float b3r[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) b3r[r] = prm[OFF_B3 + r];
 
-  const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
-  const int kg = lane / 32, col = lane % 32;
   const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
   const int ntiles = B * tiles_x * tiles_y;
+
+  auto mfma32 = [&](uint4 a, uint2 b_lo, uint2 b_hi, mfma_f32x16 acc) {
+    const mfma_u32x4 bv = {b_lo.x, b_lo.y, b_hi.x, b_hi.y};
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(mfma_bf16x8, a),
+                                                    __builtin_bit_cast(mfma_bf16x8, bv), acc, 0, 0, 0);
+  };
+  auto mfma16 = [&](uint4 a, uint2 b_lo, uint2 b_hi, mfma_f32x4 acc) {
+    const mfma_u32x4 bv = {b_lo.x, b_lo.y, b_hi.x, b_hi.y};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(mfma_bf16x8, a),
+                                                    __builtin_bit_cast(mfma_bf16x8, bv), acc, 0, 0, 0);
+  };
+  const uint2 z2 = make_uint2(0u, 0u);
+  // the lane's result (16 rows = output channels 8 j + 4 kg + i of one
+  // pixel) with bias and ReLU, zero for pixels outside the image rows, as
+  // four packed 8-byte words; layer: 0 or 1
+  auto store_rows = [&](uint16_t* dst, const mfma_f32x16& acc, int layer, bool inside) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float4 bj = bls[8 * layer + 2 * j + kg];
+      uint2 v = z2;
+      if (inside) {
+        v.x = bf16_pair(fmaxf(acc[4 * j + 0] + bj.x, 0.f), fmaxf(acc[4 * j + 1] + bj.y, 0.f));
+        v.y = bf16_pair(fmaxf(acc[4 * j + 2] + bj.z, 0.f), fmaxf(acc[4 * j + 3] + bj.w, 0.f));
+      }
+      *reinterpret_cast<uint2*>(dst + 8 * j + 4 * kg) = v;
+    }
+  };
 
   for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
     const int b = t / (tiles_x * tiles_y);
@@ -657,170 +728,160 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
     const float* v = fields[4 * b + 1];
     const float* p = fields[4 * b + 2];
     const float* ph = fields[4 * b + 3];
-    __syncthreads();  // weights staged / the previous tile's last layer done with a2x
+    __syncthreads();  // layer-3 weights and biases staged / the previous tile's last layer done with a2x
 
-    // network input on the tile + 3 (as features_kernel)
-    for (int q = threadIdx.x; q < kR0N; q += kBlock) {
-      const int ry = q / kR0W, rx = q % kR0W;
-      const int y = y0 - 3 + ry;
-      const int x = ((x0 - 3 + rx) % W + W) % W;
-      uint2 pk = make_uint2(0u, 0u);
-      if (y >= 0 && y < H) {
+    // network input on the tile + 3 (as features_kernel).  The loads of all
+    // passes are issued first, unconditionally (rows outside the image read a
+    // clamped row and are zeroed afterwards), at raised wave priority, so the
+    // tile waits for one memory latency rather than one per pass.
+    {
+      constexpr int NPI = (kR0N + kBlock - 1) / kBlock;
+      float ld[NPI][6];
+      __builtin_amdgcn_s_setprio(3);
+#pragma unroll
+      for (int it = 0; it < NPI; ++it) {
+        const int q = min((int)threadIdx.x + it * kBlock, kR0N - 1);
+        const int ry = q / kR0W, rx = q % kR0W;
+        const int y = min(max(y0 - 3 + ry, 0), H - 1);
+        // periodic x; x0 - 3 + rx lies in [-3, W + 33], one period when W >= 34
+        const int xr = x0 - 3 + rx;
+        const int x = W >= 34 ? wrap(xr, W) : (xr % W + W) % W;
         const size_t o = (size_t)y * W + x;
-        const float uc = 0.5f * (u[o] + u[(size_t)y * W + wrap(x + 1, W)]);
-        const float vn = (y + 1 < H) ? v[o + W] : 0.f;
-        const float vc = 0.5f * (v[o] + vn);
-        pk.x = (uint32_t)bf16_bits(uc / s0) | ((uint32_t)bf16_bits(vc / s1) << 16);
-        pk.y = (uint32_t)bf16_bits(p[o] / s2) | ((uint32_t)bf16_bits(ph[o] / s3) << 16);
+        ld[it][0] = u[o];
+        ld[it][1] = u[(size_t)y * W + wrap(x + 1, W)];
+        ld[it][2] = v[o];
+        ld[it][3] = v[(size_t)min(y + 1, H - 1) * W + x];
+        ld[it][4] = p[o];
+        ld[it][5] = ph[o];
       }
-      *reinterpret_cast<uint2*>(&a2x[q * 4]) = pk;
+      __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+      for (int it = 0; it < NPI; ++it) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        if (q < kR0N) {
+          const int y = y0 - 3 + q / kR0W;
+          uint2 pk = z2;
+          if (y >= 0 && y < H) {
+            const float uc = 0.5f * (ld[it][0] + ld[it][1]);
+            const float vn = (y + 1 < H) ? ld[it][3] : 0.f;
+            const float vc = 0.5f * (ld[it][2] + vn);
+            pk.x = bf16_pair(uc / s0, vc / s1);
+            pk.y = bf16_pair(ld[it][4] / s2, ld[it][5] / s3);
+          }
+          *reinterpret_cast<uint2*>(&a2x[q * 4]) = pk;
+        }
+      }
     }
     __syncthreads();
 
-    // Each wave carries two M-tiles (2 w, 2 w + 1, then + 8) with two
-    // independent accumulators, so consecutive MFMAs do not wait on each
-    // other and the B operand is read once for both.  The double-K
-    // instruction v_mfma_f32_32x32x16_bf16 takes 8 consecutive K values per
-    // lane: lane l holds A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t][l % 32]
-    // (t < 8); D is laid out as for v_mfma_f32_32x32x8.
-    // (two packed bf16 per 32-bit word, element 0 in the low half: the
-    // words are the operand as they are)
-    auto mfma16 = [&](uint2 a_lo, uint2 a_hi, uint2 b_lo, uint2 b_hi, mfma_f32x16 acc) {
-      const mfma_u32x4 av = {a_lo.x, a_lo.y, a_hi.x, a_hi.y};
-      const mfma_u32x4 bv = {b_lo.x, b_lo.y, b_hi.x, b_hi.y};
-      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(mfma_bf16x8, av),
-                                                      __builtin_bit_cast(mfma_bf16x8, bv), acc, 0, 0, 0);
-    };
-    const uint2 z2 = make_uint2(0u, 0u);
-
-    // layer 1 on the tile + 2: K = 9 taps x 4 channels; a K-step of 16
-    // holds taps 4 s + 2 kg and 4 s + 2 kg + 1 in a half-wave (taps 9-11 zero)
-    for (int m = 2 * wave; m * 32 < kR1N; m += 2 * (kBlock / 64)) {
-      const int d0 = m * 32 + col, d1 = d0 + 32;
-      const bool v0 = d0 < kR1N, v1 = d1 < kR1N;
-      const int ry0 = v0 ? d0 / kR1W : 0, rx0 = v0 ? d0 % kR1W : 0;
-      const int ry1 = v1 ? d1 / kR1W : 0, rx1 = v1 ? d1 % kR1W : 0;
-      mfma_f32x16 acc0, acc1;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
-#pragma unroll
-      for (int st = 0; st < 3; ++st) {
-        const int ta = 4 * st + 2 * kg, tb = ta + 1;
-        auto xin = [&](int ry, int rx, int tap) -> uint2 {
-          return tap < 9 ? *reinterpret_cast<const uint2*>(&a2x[((ry + tap / 3) * kR0W + rx + tap % 3) * 4]) : z2;
-        };
-        const uint2 wa_ = w1s[ta * 32 + col], wb_ = w1s[tb * 32 + col];
-        acc0 = mfma16(xin(ry0, rx0, ta), xin(ry0, rx0, tb), wa_, wb_, acc0);
-        acc1 = mfma16(xin(ry1, rx1, ta), xin(ry1, rx1, tb), wa_, wb_, acc1);
-      }
-      const float bo = bs[col];
-      // region rows inside the image: dd in [in_lo, in_hi)
+    // layer 1 on the tile + 2: column blocks n = wave + 4 i, two at a time
+    // with independent accumulators; the lane's pixel is column col
+    {
       const int in_lo = max(0, 2 - y0) * kR1W, in_hi = min(kR1H, H - y0 + 2) * kR1W;
+      for (int n0 = wave; n0 < kN1; n0 += 2 * (kBlock / 64)) {
+        const int n1 = n0 + kBlock / 64;
+        const int d0 = n0 * 32 + col, d1 = n1 * 32 + col;
+        const bool v0 = d0 < kR1N, v1 = d1 < kR1N;
+        const int ry0 = v0 ? d0 / kR1W : 0, rx0 = v0 ? d0 % kR1W : 0;
+        const int ry1 = v1 ? d1 / kR1W : 0, rx1 = v1 ? d1 % kR1W : 0;
+        mfma_f32x16 acc0, acc1;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+        for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int dd = (m + h) * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
-          if (dd < kR1N) {
-            const float a = h ? acc1[r] : acc0[r];
-            a1[dd * kAS + col] = (dd >= in_lo && dd < in_hi) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
-          }
+        for (int st = 0; st < 3; ++st) {
+          const int ta = 4 * st + 2 * kg, tb = ta + 1;
+          auto xin = [&](int ry, int rx, int tap) -> uint2 {
+            return tap < 9 ? *reinterpret_cast<const uint2*>(&a2x[((ry + tap / 3) * kR0W + rx + tap % 3) * 4]) : z2;
+          };
+          acc0 = mfma32(w1r[st], xin(ry0, rx0, ta), xin(ry0, rx0, tb), acc0);
+          acc1 = mfma32(w1r[st], xin(ry1, rx1, ta), xin(ry1, rx1, tb), acc1);
         }
+        if (v0) store_rows(&a1[d0 * kAS], acc0, 0, d0 >= in_lo && d0 < in_hi);
+        if (v1) store_rows(&a1[d1 * kAS], acc1, 0, d1 >= in_lo && d1 < in_hi);
       }
     }
     __syncthreads();
 
-    // layers 2 and 3: the 32-channel implicit GEMM on two M-tiles; the
-    // destination pixel (ry, rx) reads the source region of width SW (two
-    // cells wider) at (ry + dy + 1, rx + dx + 1); a K-step of 16 is one tap
-    // and 16 channels, 8 per half-wave (two 8-byte LDS reads).  Rows of
-    // invalid pixels read pixel (0, 0) of the region and are never stored.
-    auto conv32x2 = [&](const uint16_t* src, int SW, int ry0, int rx0, int ry1, int rx1, const uint2* wt,
-                        bool cols4, mfma_f32x16& acc0, mfma_f32x16& acc1) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
-#pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        const uint16_t* sp0 = src + ((ry0 + tap / 3) * SW + rx0 + tap % 3) * kAS;
-        const uint16_t* sp1 = src + ((ry1 + tap / 3) * SW + rx1 + tap % 3) * kAS;
-#pragma unroll
-        for (int c = 0; c < 32; c += 16) {
-          const int c0 = c + 8 * kg;
-          const int kc = (tap * 32 + c0) / 4;  // first 4-value chunk of the lane's 8 K values
-          uint2 b_lo = z2, b_hi = z2;
-          if (!cols4) {
-            b_lo = wt[kc * 32 + col];
-            b_hi = wt[(kc + 1) * 32 + col];
-          } else if (col < 4) {
-            b_lo = wt[kc * 4 + col];
-            b_hi = wt[(kc + 1) * 4 + col];
-          }
-          acc0 = mfma16(*reinterpret_cast<const uint2*>(sp0 + c0), *reinterpret_cast<const uint2*>(sp0 + c0 + 4),
-                        b_lo, b_hi, acc0);
-          acc1 = mfma16(*reinterpret_cast<const uint2*>(sp1 + c0), *reinterpret_cast<const uint2*>(sp1 + c0 + 4),
-                        b_lo, b_hi, acc1);
-        }
-      }
-    };
-
-    // layer 2 on the tile + 1
-    for (int m = 2 * wave; m * 32 < kR2N; m += 2 * (kBlock / 64)) {
-      const int d0 = m * 32 + col, d1 = d0 + 32;
-      const bool v0 = d0 < kR2N, v1 = d1 < kR2N;
-      mfma_f32x16 acc0, acc1;
-      conv32x2(a1, kR1W, v0 ? d0 / kR2W : 0, v0 ? d0 % kR2W : 0, v1 ? d1 / kR2W : 0, v1 ? d1 % kR2W : 0, w2s,
-               false, acc0, acc1);
-      const float bo = bs[32 + col];
+    // layer 2 on the tile + 1: column blocks wave, wave + 4, wave + 8 with
+    // three independent accumulators; K step s reads tap s / 2, channels
+    // 16 (s % 2) + 8 kg .. + 7 of the source pixel (two 8-byte LDS reads)
+    {
       const int in_lo = max(0, 1 - y0) * kR2W, in_hi = min(kR2H, H - y0 + 1) * kR2W;
+      int dd[3];
+      const uint16_t* sp[3];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int i = 0; i < 3; ++i) {
+        dd[i] = (wave + 4 * i) * 32 + col;
+        const bool vi = dd[i] < kR2N;
+        sp[i] = a1 + ((vi ? dd[i] / kR2W : 0) * kR1W + (vi ? dd[i] % kR2W : 0)) * kAS + 8 * kg;
+      }
+      mfma_f32x16 acc[3];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int dd = (m + h) * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
-          if (dd < kR2N) {
-            const float a = h ? acc1[r] : acc0[r];
-            a2x[dd * kAS + col] = (dd >= in_lo && dd < in_hi) ? bf16_bits(fmaxf(a + bo, 0.f)) : (uint16_t)0;
-          }
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+#pragma unroll
+      for (int st = 0; st < 18; ++st) {
+        const int tap = st / 2, off = ((tap / 3) * kR1W + tap % 3) * kAS + 16 * (st % 2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (i == 2 && wave + 8 >= kN2) continue;  // wave-uniform: no third block
+          const uint16_t* q = sp[i] + off;
+          acc[i] = mfma32(w2r[st], *reinterpret_cast<const uint2*>(q), *reinterpret_cast<const uint2*>(q + 4), acc[i]);
         }
       }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (dd[i] < kR2N) store_rows(&a2x[dd[i] * kAS], acc[i], 1, dd[i] >= in_lo && dd[i] < in_hi);
     }
     __syncthreads();
 
-    // layer 3 on the tile: M-tile m is tile row m (32 columns), rows 2 w and
-    // 2 w + 1 per wave; lanes with output column < 4 write the result and
-    // the phi column's tile sum
+    // layer 3 on the tile: 16-pixel blocks, tile rows 2 w and 2 w + 1 per
+    // wave (two blocks each); K step s is tap s, channels 8 q16 .. + 7 of the
+    // source pixel; lanes 0-15 hold the 4 output channels of their pixel
     float psum = 0.f;
     {
-      static_assert(kTH == 2 * (kBlock / 64), "two tile rows per wave");
-      const int m = 2 * wave;
-      mfma_f32x16 acc0, acc1;
-      conv32x2(a2x, kR2W, m, col, m + 1, col, w3s, true, acc0, acc1);
-      if (col < 4) {
-        const float bo = bs[64 + col];
+      static_assert(kTH == 2 * (kBlock / 64) && kTW == 32, "two tile rows of two 16-pixel blocks per wave");
+      mfma_f32x4 acc[4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int y = y0 + m + h;
-          if (y >= H) continue;
+      for (int i = 0; i < 4; ++i) acc[i] = mfma_f32x4{0.f, 0.f, 0.f, 0.f};
+      const uint16_t* sp[4];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int xc = x0 + 8 * (r / 4) + 4 * kg + (r % 4);
-            if (xc < W) {
-              const float val = (h ? acc1[r] : acc0[r]) + bo;
-              out[(((size_t)b * H + y) * W + xc) * 4 + col] = val;
-              if (col == 3) psum += val;
-            }
+      for (int i = 0; i < 4; ++i) {
+        const int ry = 2 * wave + i / 2, rx = 16 * (i % 2) + c16;
+        sp[i] = a2x + (ry * kR2W + rx) * kAS + 8 * q16;
+      }
+#pragma unroll
+      for (int st = 0; st < 9; ++st) {
+        const uint4 a = w3s[st * 64 + lane];
+        const int off = ((st / 3) * kR2W + st % 3) * kAS;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint16_t* q = sp[i] + off;
+          acc[i] = mfma16(a, *reinterpret_cast<const uint2*>(q), *reinterpret_cast<const uint2*>(q + 4), acc[i]);
+        }
+      }
+      if (q16 == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int y = y0 + 2 * wave + i / 2, xc = x0 + 16 * (i % 2) + c16;
+          if (y < H && xc < W) {
+            const float4 val = make_float4(acc[i][0] + b3r[0], acc[i][1] + b3r[1], acc[i][2] + b3r[2], acc[i][3] + b3r[3]);
+            *reinterpret_cast<float4*>(&out[(((size_t)b * H + y) * W + xc) * 4]) = val;
+            psum += val.w;
           }
         }
       }
     }
-    // tile sum of the phi output: lanes 3 and 35 of each wave, then the waves
-    psum += __shfl_xor(psum, 32, 64);
-    if (lane == 3) red[wave] = psum;
+    // tile sum of the phi output: lanes 0-15 of each wave, then the waves
+#pragma unroll
+    for (int o = 8; o >= 1; o /= 2) psum += __shfl_xor(psum, o, 64);
+    if (lane == 0) red[wave] = psum;
     __syncthreads();
     if (threadIdx.x == 0) {
-      float s = 0.f;
-      for (int w = 0; w < kBlock / 64; ++w) s += red[w];
-      partial[t] = s;
+      float sum = 0.f;
+      for (int w = 0; w < kBlock / 64; ++w) sum += red[w];
+      partial[t] = sum;
     }
   }
 }
