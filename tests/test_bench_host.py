@@ -34,3 +34,23 @@ def test_traffic_entries_are_guarded_by_the_kernel_hash():
     assert len(h) == 16
     # an entry is used only while its hash matches the kernel sources
     assert bench.measured_traffic("no_such_kernel", "fp32") is None
+
+
+def test_committed_traffic_belongs_to_the_current_kernels():
+    """profiles/traffic.json holds rocprofv3 FETCH_SIZE + WRITE_SIZE bytes for
+    every kernel of the 3-D step in both precisions, measured on the kernel
+    sources as they are now, and each figure lies near that kernel's
+    algorithmic bytes at 256^3 (each field read once and written once)."""
+    import json
+
+    data = json.load(open(bench.TRAFFIC_FILE))
+    fields = {"flow_stage1": 9, "flow_stage2": 13, "flow_stage3": 16,
+              "ch_rk4_stage1": 6, "ch_rk4_stage2": 8, "ch_rk4_stage3": 8, "ch_rk4_stage4": 7}
+    for prec, esize in (("fp32", 4), ("fp64", 8)):
+        for k, nf in fields.items():
+            ent = data[f"{k}:{prec}"]
+            assert ent["csrc_hash"] == bench.csrc_hash(), k
+            got = bench.measured_traffic(k, prec)
+            assert got == ent["bytes_per_launch"] == ent["fetch_bytes"] + ent["write_bytes"]
+            ratio = got / (nf * 256 ** 3 * esize)
+            assert 0.95 < ratio < 1.5, (k, prec, ratio)
