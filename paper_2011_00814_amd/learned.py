@@ -432,6 +432,7 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
 
     fine_ms = coarse_ms = net_ms = 0.0
     series = []
+    record = []  # per checkpoint: indicator, finiteness and interface heights of the learned run, reference
     lam_steps = nx / 0.05  # fine steps per T_c = lambda / U_c
     for seg in range(checkpoints):
         fine_ms += timed(ens_f.stream, lambda: ens_f.run(seg_f))
@@ -446,6 +447,7 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
         ref = heights(phi_of(rstore.ptrs(range(B))))
         h_c = heights(phi_of(Lr.state_pointers([ens_c.case(b) for b in range(B)])))
         h_n = heights(phi_of(Lr.state_pointers([ens_n.case(b) for b in range(B)])))
+        record.append((rms.copy(), flags_n.copy(), h_n, ref))
         fsteps = (seg + 1) * seg_f
         learned = err(h_n, ref, np.where(fallen, 1, flags_n), exact=fallen)
         learned.update(fallback_to_fine=int(fallen.sum()), indicator_rms_max=round(float(np.nanmax(rms)), 4))
@@ -456,13 +458,32 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
     # the fine solver's cost for the cases that fell back (time per case of the batched fine run)
     fallback_ms = fine_ms * float(fallen.sum()) / B
 
-    def horizon(kind):
+    def horizon_of(mins):
         h = None
-        for row in series:
-            if row[kind]["min_case_columns_within_1_cell"] < 0.95:
+        for row, m in zip(series, mins):
+            if m < 0.95:
                 break
             h = row
         return {"fine_steps": h["fine_steps"] if h else 0, "t_over_Tc": h["t_over_Tc"] if h else 0.0}
+
+    def horizon(kind):
+        return horizon_of([row[kind]["min_case_columns_within_1_cell"] for row in series])
+
+    def operating_point(thr):
+        # the same learned run with another fallback threshold: falling back
+        # changes only which cases count as exact and what they cost
+        fl = np.zeros(B, dtype=bool)
+        mins, last_err = [], None
+        for rms_s, flags_s, h_s, ref_s in record:
+            fl |= (flags_s == 0) | ~(rms_s <= thr)
+            last_err = err(h_s, ref_s, np.where(fl, 1, flags_s), exact=fl)
+            mins.append(last_err["min_case_columns_within_1_cell"])
+        fb = fine_ms * float(fl.sum()) / B
+        return {"indicator_threshold": thr, "fallback_to_fine": int(fl.sum()),
+                "speedup_vs_fine": round(fine_ms / (net_ms + fb), 2),
+                "horizon_95pct_columns_every_case": horizon_of(mins),
+                "columns_within_1_cell_at_end": last_err["columns_within_1_cell"],
+                "mean_err_mean_at_end": round(last_err["mean_err_mean"], 4)}
     res = {
         "cases": B, "fine_steps": checkpoints * seg_f, "coarse_steps": checkpoints * seg_c, "factor": factor,
         "grid_fine": [nx, ny], "grid_coarse": [Wc, H], "error_unit": f"coarse cells ({factor} fine cells)",
@@ -475,6 +496,7 @@ def evaluate(net, in_scale, out_scale, seeds, fine_steps, factor=4, nx=256, ny=1
         "horizon_95pct_columns_every_case": {"plain_coarse": horizon("plain_coarse"),
                                              "learned_coarse": horizon("learned_coarse")},
         "learned_non_finite": int((flags_n == 0).sum()),
+        "operating_points": [operating_point(t) for t in (2.0, 1.0, 0.5)],
         "checkpoints": series,
     }
     log(f"[learned] evaluation: {res}")
