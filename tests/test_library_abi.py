@@ -255,3 +255,22 @@ def test_unstable_time_step_rejected_on_host(G):
     assert _stability_code(G, prob) == G.GPE_EUNSTABLE
     prob["allow_unstable"] = 1
     assert _stability_code(G, prob) == G.GPE_EWORKSPACE
+
+
+def test_hbm_stream_probe_rejects_invalid_arguments(G):
+    """gpe_hbm_stream validates its arguments before it launches anything
+    (the pointers here are never dereferenced)."""
+    L = G.lib()
+    A, B = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    bad = [
+        (G.GPE_STREAM_COPY, A, B, 0, 1),                       # no bytes
+        (G.GPE_STREAM_COPY, A, B, 24, 1),                      # not a multiple of 16
+        (G.GPE_STREAM_COPY, ctypes.c_void_p(None), B, 64, 1),  # no destination
+        (G.GPE_STREAM_READ, A, ctypes.c_void_p(None), 64, 1),  # no source to read
+        (G.GPE_STREAM_COPY, ctypes.c_void_p(0x10008), B, 64, 1),  # misaligned destination
+        (G.GPE_STREAM_COPY, A, ctypes.c_void_p(0x20004), 64, 1),  # misaligned source
+        (G.GPE_STREAM_COPY, A, B, 64, -1),                     # negative work-group count
+        (7, A, B, 64, 1),                                      # unknown mode
+    ]
+    for mode, dst, src, nbytes, wg in bad:
+        assert L.gpe_hbm_stream(mode, dst, src, nbytes, wg, None) == G.GPE_EINVAL, (mode, nbytes, wg)
