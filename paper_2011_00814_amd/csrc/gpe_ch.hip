@@ -147,10 +147,10 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
       rm = mirrored ? up : dn;
       rnode = rk;
     }
-    constexpr int EXN = TX + 2;
     constexpr int EN = (DIM == 3) ? (TX + 2) * (TY + 2) : TX + 2;
     for (int e = (int)threadIdx.x; e < EN; e += NT) {
-      const int ex = e % EXN, ey = e / EXN;
+      int ex, ey;
+      region_pos<TX + 2, (DIM == 3) ? TY + 2 : 1>(e, ex, ey);
       const int q = ((DIM == 3) ? (ey + 1) * PX : 0) + ex + 1;
       const T* b = lds + q;
       T* bq = ldq + ey * QX + ex;

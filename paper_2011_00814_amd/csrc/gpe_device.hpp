@@ -196,6 +196,28 @@ __device__ __forceinline__ void wave_prio() {
   __builtin_amdgcn_s_setprio(P);
 }
 
+// Position (ex, ey) of index e in a W x H region of a staged LDS plane whose
+// rows are longer than W.  Enumerated row by row, a 32-lane half-wave that
+// crosses a row break skips the row's padding and hits two banks twice.  For
+// 32 < W < 64 the first 32 H indices therefore run along rows of 32 columns
+// (32 consecutive LDS words per half-wave) and the last W - 32 columns
+// follow, interleaved across them.  Other shapes are enumerated row by row.
+template <int W, int H>
+__device__ __forceinline__ void region_pos(int e, int& ex, int& ey) {
+  constexpr int X = W - 32;
+  if (H == 1 || X <= 0 || X >= 32) {
+    ex = e % W;
+    ey = e / W;
+  } else if (e < 32 * H) {
+    ex = e & 31;
+    ey = e >> 5;
+  } else {
+    const int t = e - 32 * H;
+    ex = 32 + t % X;
+    ey = t / X;
+  }
+}
+
 // Reciprocal: hardware approximation (1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }

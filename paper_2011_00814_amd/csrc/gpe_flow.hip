@@ -232,11 +232,11 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   // s0, sp of the 3-plane rings) on positions [0, T] of the tile, into the
   // edge slot of plane k; with the in-plane edges of plane k when xy is set
   auto edges = [&](int k, int s0, int sp, bool xy) {
-    constexpr int EX_N = TX + 1;
     constexpr int EN = (DIM == 3) ? (TX + 1) * (TY + 1) : TX + 1;
     const int e0 = (k & 1) * PLANE, e1 = PLANE - e0;
     for (int e = (int)threadIdx.x; e < EN; e += NT) {
-      const int ex = e % EX_N, ey = e / EX_N;
+      int ex, ey;
+      region_pos<TX + 1, (DIM == 3) ? TY + 1 : 1>(e, ex, ey);
       const int q = ((DIM == 3) ? (ey + 2) * PX : 0) + ex + 2;
       T* d = lds + q;
       const T* E0 = d + S_ET * PLANE + e0;
@@ -314,10 +314,10 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
 
     // div u and mu (unless staged) of plane k on [-1, T-1] (LDS positions 1 .. T+1)
     {
-      constexpr int EX_N = TX + 1;
       constexpr int EN = (DIM == 3) ? (TX + 1) * (TY + 1) : TX + 1;
       for (int e = (int)threadIdx.x; e < EN; e += NT) {
-        const int ex = e % EX_N, ey = e / EX_N;
+        int ex, ey;
+        region_pos<TX + 1, (DIM == 3) ? TY + 1 : 1>(e, ex, ey);
         const int q = ((DIM == 3) ? (ey + 1) * PX : 0) + ex + 1;
         T* b = lds + q;
         if (!MU_STORED)
