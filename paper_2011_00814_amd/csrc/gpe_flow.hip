@@ -230,11 +230,15 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   };
   // edge fluxes of the Z-directed edges between planes k and k+1 (ring slots
   // s0, sp of the 3-plane rings) on positions [0, T] of the tile, into the
-  // edge slot of plane k; with the in-plane edges of plane k when xy is set
+  // edge slot of plane k; with the in-plane edges of plane k when xy is set.
+  // The region has a few positions more than the work-group has threads; the
+  // thread index is rotated by one wave so that this loop's extra positions
+  // fall to the second wave and those of the mu / div loop to the first.
   auto edges = [&](int k, int s0, int sp, bool xy) {
     constexpr int EN = (DIM == 3) ? (TX + 1) * (TY + 1) : TX + 1;
+    constexpr int ROT = NT > 64 ? NT - 64 : 0;
     const int e0 = (k & 1) * PLANE, e1 = PLANE - e0;
-    for (int e = (int)threadIdx.x; e < EN; e += NT) {
+    for (int e = ((int)threadIdx.x + ROT) % NT; e < EN; e += NT) {
       int ex, ey;
       region_pos<TX + 1, (DIM == 3) ? TY + 1 : 1>(e, ex, ey);
       const int q = ((DIM == 3) ? (ey + 2) * PX : 0) + ex + 2;
