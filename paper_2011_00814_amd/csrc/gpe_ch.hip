@@ -230,9 +230,39 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
     }
   };
 
+  // Corner sums of one plane at the own column, for the corner links
+  // (+-1, +-1, +-1) of the 3-D lattices: q[0] the sum of mu over the four
+  // in-plane diagonal neighbours; conservative form q[1] = sum of
+  // sx F_X + sy F_Y and q[2] = sum of F_Z over them; advective form q[1..3]
+  // = the sums of sx phi, sy phi and phi.  The output of plane k takes them
+  // for planes k + 1 and k - 1; the sums of plane m are formed once, right
+  // after plane m is derived, and carried in registers until the output of
+  // plane m + 1 (instead of reading the same 16 LDS words again there).
+  auto corners = [&](auto sm, T* q) {
+    constexpr int SC = decltype(sm)::value;
+    const T* M = Q0 + (S_MU + SC) * QPLANE;
+    const T* X = Q0 + (S_FX + SC) * QPLANE;
+    q[0] = (M[1 + QEY] + M[1 - QEY]) + (M[-1 + QEY] + M[-1 - QEY]);
+    if (!ADV) {
+      const T* Y = Q0 + (S_FY + SC) * QPLANE;
+      const T* Z = Q0 + (S_FZ + SC) * QPLANE;
+      q[1] = ((X[1 + QEY] + X[1 - QEY]) - (X[-1 + QEY] + X[-1 - QEY])) +
+             ((Y[1 + QEY] + Y[-1 + QEY]) - (Y[1 - QEY] + Y[-1 - QEY]));
+      q[2] = (Z[1 + QEY] + Z[1 - QEY]) + (Z[-1 + QEY] + Z[-1 - QEY]);
+    } else {
+      q[1] = (X[1 + QEY] + X[1 - QEY]) - (X[-1 + QEY] + X[-1 - QEY]);
+      q[2] = (X[1 + QEY] + X[-1 + QEY]) - (X[1 - QEY] + X[-1 - QEY]);
+      q[3] = (X[1 + QEY] + X[1 - QEY]) + (X[-1 + QEY] + X[-1 - QEY]);
+    }
+  };
+  constexpr int NC = ADV ? 4 : 3;
+  T cq_m[4] = {T(0), T(0), T(0), T(0)};  // planes k - 1, k, k + 1
+  T cq_0[4] = {T(0), T(0), T(0), T(0)};
+  T cq_p[4] = {T(0), T(0), T(0), T(0)};
+
   // output at plane k whose ring slot is S0 (planes k-1, k+1 in SM, SP);
   // phc = phi(k) at the own cell
-  auto output = [&](int k, auto s0, T phc, T ps, T ac, T ucx, T ucy, T ucz) {
+  auto output = [&](int k, auto s0, T phc, T ps, T ac, T ucx, T ucy, T ucz, const T* cp, const T* cm) {
     constexpr int S0 = decltype(s0)::value;
     constexpr int SM = (S0 + 2) % 3, SP = (S0 + 1) % 3;
     const T* M0 = Q0 + (S_MU + S0) * QPLANE;
@@ -271,9 +301,11 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
         flux = ucx * gx + ucz * gz;
       }
     } else {
-      const T s1 = ((M0[1] - mc) + (M0[-1] - mc)) + ((M0[QEY] - mc) + (M0[-QEY] - mc)) +
-                   ((Mp[0] - mc) + (Mm[0] - mc));
-      lap = c.w1 * s1;
+      // Laplacian of mu summed first: mu has no offset in the bulk (it
+      // vanishes there), so the neighbour sums lose nothing against the
+      // differences, at half the instructions
+      const T s1 = ((M0[1] + M0[-1]) + (M0[QEY] + M0[-QEY])) + (Mp[0] + Mm[0]);
+      lap = fma(T(-6) * c.w1, mc, c.w1 * s1);
       // advective form: isotropic gradient of phi, held in the F_X ring
       T gx = T(0), gy = T(0), gz = T(0);
       if (!ADV) {
@@ -284,10 +316,9 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
         gz = c.w1 * (Xp[0] - Xm[0]);
       }
       if (c.w2 != T(0)) {
-        const T s2 = ((M0[1 + QEY] - mc) + (M0[1 - QEY] - mc) + (M0[-1 + QEY] - mc) + (M0[-1 - QEY] - mc)) +
-                     ((Mp[1] - mc) + (Mp[-1] - mc) + (Mp[QEY] - mc) + (Mp[-QEY] - mc)) +
-                     ((Mm[1] - mc) + (Mm[-1] - mc) + (Mm[QEY] - mc) + (Mm[-QEY] - mc));
-        lap += c.w2 * s2;
+        const T s2 = ((M0[1 + QEY] + M0[1 - QEY]) + (M0[-1 + QEY] + M0[-1 - QEY])) +
+                     ((Mp[1] + Mp[-1]) + (Mp[QEY] + Mp[-QEY])) + ((Mm[1] + Mm[-1]) + (Mm[QEY] + Mm[-QEY]));
+        lap += c.w2 * fma(T(-12), mc, s2);
         if (!ADV) {
           // edges: XY in plane k, XZ and YZ in planes k +- 1
           const T exy = ((X0[1 + QEY] + X0[1 - QEY]) - (X0[-1 + QEY] + X0[-1 - QEY])) +
@@ -308,28 +339,15 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
         }
       }
       if (c.w3 != T(0)) {
-        const T s3 = ((Mp[1 + QEY] - mc) + (Mp[1 - QEY] - mc) + (Mp[-1 + QEY] - mc) + (Mp[-1 - QEY] - mc)) +
-                     ((Mm[1 + QEY] - mc) + (Mm[1 - QEY] - mc) + (Mm[-1 + QEY] - mc) + (Mm[-1 - QEY] - mc));
-        lap += c.w3 * s3;
+        // corner links (+-1, +-1, +-1): the per-plane corner sums of planes
+        // k + 1 (cp) and k - 1 (cm), formed by corners()
+        lap += c.w3 * fma(T(-8), mc, cp[0] + cm[0]);
         if (!ADV) {
-          // corners (sx, sy, sz): sx F_X + sy F_Y + sz F_Z at planes k +- 1
-          auto corner = [&](const T* X, const T* Y) {
-            return ((X[1 + QEY] + X[1 - QEY]) - (X[-1 + QEY] + X[-1 - QEY])) +
-                   ((Y[1 + QEY] + Y[-1 + QEY]) - (Y[1 - QEY] + Y[-1 - QEY]));
-          };
-          const T zs = ((Zp[1 + QEY] + Zp[1 - QEY]) + (Zp[-1 + QEY] + Zp[-1 - QEY])) -
-                       ((Zm[1 + QEY] + Zm[1 - QEY]) + (Zm[-1 + QEY] + Zm[-1 - QEY]));
-          flux += c.w3 * ((corner(Xp, Yp) + corner(Xm, Ym)) + zs);
+          flux += c.w3 * ((cp[1] + cm[1]) + (cp[2] - cm[2]));
         } else {
-          // corner links (+-1, +-1, +-1) of phi in planes k +- 1
-          const T* Pp = Xp;
-          const T* Pm = Xm;
-          auto cx = [&](const T* P) { return (P[1 + QEY] + P[1 - QEY]) - (P[-1 + QEY] + P[-1 - QEY]); };
-          auto cy = [&](const T* P) { return (P[1 + QEY] + P[-1 + QEY]) - (P[1 - QEY] + P[-1 - QEY]); };
-          auto cs = [&](const T* P) { return (P[1 + QEY] + P[1 - QEY]) + (P[-1 + QEY] + P[-1 - QEY]); };
-          gx += c.w3 * (cx(Pp) + cx(Pm));
-          gy += c.w3 * (cy(Pp) + cy(Pm));
-          gz += c.w3 * (cs(Pp) - cs(Pm));
+          gx += c.w3 * (cp[1] + cm[1]);
+          gy += c.w3 * (cp[2] + cm[2]);
+          gz += c.w3 * (cp[3] - cm[3]);
         }
       }
       if (ADV) flux = (ucx * gx + ucy * gy) + ucz * gz;
@@ -405,7 +423,16 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
       uc_next[2] = L0[(S_SZ + S1) * PLANE] + L0[(S_SZ + S2) * PLANE];
     }
     __syncthreads();
-    if (k >= z0 && active) output(k, sk, phc, phis_cur, acc_cur, uc_cur[0], uc_cur[1], uc_cur[2]);
+    const bool corner_links = DIM == 3 && c.w3 != T(0);
+    if (corner_links) corners(std::integral_constant<int, S1>{}, cq_p);
+    if (k >= z0 && active) output(k, sk, phc, phis_cur, acc_cur, uc_cur[0], uc_cur[1], uc_cur[2], cq_p, cq_m);
+    if (corner_links) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        cq_m[q] = cq_0[q];
+        cq_0[q] = cq_p[q];
+      }
+    }
     phis_cur = phis_next;
     acc_cur = acc_next;
     if (ADV) {
