@@ -314,6 +314,17 @@ int gpe_set_step_time(gpe_state* s, int64_t step, double t);
 int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names,
                      double* ms, double* bytes);
 
+/* As gpe_kernel_times, with events only at the boundaries of the kernels
+ * selected by mask (bit q: the q-th kernel of a step, in the order of the
+ * names; bits beyond the step's kernel count are ignored).  The other
+ * launches run back to back without events between them, so the steps run
+ * as they do untimed except around the selected kernels.  ms[q] is 0 for a
+ * kernel not selected; names and bytes are filled for all.  Returns the
+ * number of kernels, or GPE_EINVAL when no kernel of the step is selected
+ * (or for the argument errors of gpe_kernel_times). */
+int gpe_kernel_times_masked(gpe_state* s, int64_t nsteps, uint32_t mask, int max,
+                            const char** names, double* ms, double* bytes);
+
 /* ------------------------------------------------------------------------
  * Batched ensemble: many independent 2-D (or many axisymmetric) grids of
  * different sizes and parameters advanced together, one kernel launch per

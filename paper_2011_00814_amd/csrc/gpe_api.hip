@@ -173,9 +173,12 @@ Consts<T> make_consts(const gpe_params* p, int dim) {
 // ---- kernel sequence of one time step ----------------------------------
 // Chained timing events: one before the first kernel of a step and one after
 // every kernel, so kernel q of a step lasts from event q to event q + 1.
+// Only the boundaries of the kernels selected by mask get an event.
 struct KernelTimer {
   hipEvent_t* ev = nullptr;  // this step's events
   int n = 0;
+  uint32_t mask = ~0u;
+  bool wants(int q) const { return ((mask >> q) & 1u) || (q > 0 && ((mask >> (q - 1)) & 1u)); }
 };
 
 // Longest Z chunk per work-group (planes): see choose_zchunk.
@@ -210,7 +213,9 @@ hipError_t enqueue_step_t(gpe_state* s, KernelTimer* kt) {
   const int geom = s->P.geometry;
   hipError_t e = hipSuccess;
   auto mark = [&]() {
-    if (kt) (void)hipEventRecord(kt->ev[kt->n++], s->stream);
+    if (!kt) return;
+    if (kt->wants(kt->n)) (void)hipEventRecord(kt->ev[kt->n], s->stream);
+    ++kt->n;
   };
   mark();
   const int zf = flow_zchunk(s, sizeof(T));
@@ -664,11 +669,13 @@ int gpe_set_step_time(gpe_state* s, int64_t step, double t) {
   return GPE_OK;
 }
 
-int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, double* ms,
-                     double* bytes) {
+int gpe_kernel_times_masked(gpe_state* s, int64_t nsteps, uint32_t mask, int max, const char** names, double* ms,
+                            double* bytes) {
   if (!s || nsteps < 1 || max < 1 || !names || !ms || !bytes) return GPE_EINVAL;
   const int nk = s->dim == 3 ? 7 : 5;
   if (max < nk) return GPE_EINVAL;
+  mask &= (1u << nk) - 1u;
+  if (mask == 0) return GPE_EINVAL;
   static const char* n3[7] = {"flow_stage1", "flow_stage2", "flow_stage3", "ch_rk4_stage1",
                               "ch_rk4_stage2", "ch_rk4_stage3", "ch_rk4_stage4"};
   static const char* n2[5] = {"flow_stage1", "flow_stage2", "flow_stage3", "ch_rk2_stage1",
@@ -678,13 +685,16 @@ int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, 
   const double f2[5] = {7, 10, 12, 5, 6};
   // all steps are enqueued back to back (no host synchronisation between
   // them), then read once
+  KernelTimer proto;
+  proto.mask = mask;
+  // events of the boundaries in use only (the others stay null)
   std::vector<hipEvent_t> ev((size_t)nsteps * (nk + 1), nullptr);
   int rc = GPE_OK;
-  for (auto& x : ev)
-    if (hipEventCreate(&x) != hipSuccess) { rc = GPE_EHIP; break; }
+  for (size_t i = 0; i < ev.size() && rc == GPE_OK; ++i)
+    if (proto.wants((int)(i % (size_t)(nk + 1))) && hipEventCreate(&ev[i]) != hipSuccess) rc = GPE_EHIP;
   std::vector<double> acc(nk, 0.0);
   for (int64_t st = 0; st < nsteps && rc == GPE_OK; ++st) {
-    KernelTimer kt;
+    KernelTimer kt = proto;
     kt.ev = ev.data() + (size_t)st * (nk + 1);
     if (enqueue_step(s, &kt) != hipSuccess) { rc = GPE_EHIP; break; }
     s->step += 1;
@@ -693,6 +703,7 @@ int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, 
   for (int64_t st = 0; st < nsteps && rc == GPE_OK; ++st) {
     const hipEvent_t* e = ev.data() + (size_t)st * (nk + 1);
     for (int q = 0; q < nk; ++q) {
+      if (!((mask >> q) & 1u)) continue;
       float t = 0;
       if (hipEventElapsedTime(&t, e[q], e[q + 1]) != hipSuccess) { rc = GPE_EHIP; break; }
       acc[q] += t;
@@ -708,6 +719,10 @@ int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, 
     bytes[q] = (s->dim == 3 ? f3[q] : f2[q]) * (double)s->ncell * (double)s->esize;
   }
   return nk;
+}
+
+int gpe_kernel_times(gpe_state* s, int64_t nsteps, int max, const char** names, double* ms, double* bytes) {
+  return gpe_kernel_times_masked(s, nsteps, ~0u, max, names, ms, bytes);
 }
 
 void gpe_destroy(gpe_state* s) {

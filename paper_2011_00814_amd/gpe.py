@@ -125,6 +125,10 @@ def lib():
         L.gpe_kernel_times.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                        ctypes.POINTER(f64), ctypes.POINTER(f64)]
         L.gpe_kernel_times.restype = ctypes.c_int
+        L.gpe_kernel_times_masked.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(f64),
+                                              ctypes.POINTER(f64)]
+        L.gpe_kernel_times_masked.restype = ctypes.c_int
         L.gpe_destroy.argtypes = [vp]
         L.gpe_destroy.restype = None
         L.gpe_strerror.argtypes = [ctypes.c_int]
@@ -258,6 +262,16 @@ def gpe_kernel_times(h, nsteps: int, maxk: int = 16):
     rc = lib().gpe_kernel_times(h, int(nsteps), maxk, names, ms, nb)
     if rc < 0:
         raise GpeError(rc, "gpe_kernel_times")
+    return [(names[q].decode(), ms[q], nb[q]) for q in range(rc)]
+
+
+def gpe_kernel_times_masked(h, nsteps: int, mask: int, maxk: int = 16):
+    names = (ctypes.c_char_p * maxk)()
+    ms = (f64 * maxk)()
+    nb = (f64 * maxk)()
+    rc = lib().gpe_kernel_times_masked(h, int(nsteps), int(mask) & 0xFFFFFFFF, maxk, names, ms, nb)
+    if rc < 0:
+        raise GpeError(rc, "gpe_kernel_times_masked")
     return [(names[q].decode(), ms[q], nb[q]) for q in range(rc)]
 
 
@@ -495,8 +509,10 @@ class Solver(_Grid):
     def run(self, n: int):
         gpe_run_n(self.h, n)
 
-    def kernel_times(self, nsteps: int):
-        return gpe_kernel_times(self.h, nsteps)
+    def kernel_times(self, nsteps: int, mask=None):
+        if mask is None:
+            return gpe_kernel_times(self.h, nsteps)
+        return gpe_kernel_times_masked(self.h, nsteps, mask)
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -22,7 +22,7 @@ def G():
 
 def test_exports_every_header_symbol(G):
     names = G.header_functions()
-    assert len(names) == 24
+    assert len(names) == 25
     L = G.lib()
     for n in names:
         assert hasattr(L, n), n
