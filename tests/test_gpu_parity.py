@@ -252,6 +252,33 @@ def test_graph_replay_equals_eager_bitwise(gpe):
                 assert np.array_equal(a[k], b[k]), (name, k)
 
 
+def test_kernel_times_run_the_plain_steps(gpe):
+    """The timing entry points advance the state exactly as untimed steps do
+    (bitwise), time the kernels they select and no others, fill the names
+    and bytes of every kernel, and reject a selection with no kernel of the
+    step in it (before running anything)."""
+    prob, st = _case("bubble3d_walls", precision="fp32")
+    ref, _ = _run_gpu(gpe, prob, st, 9)
+    s = gpe.Solver(prob, st)
+    full = s.kernel_times(3)
+    part = s.kernel_times(3, mask=1 << 2)
+    ends = s.kernel_times(3, mask=(1 << 0) | (1 << 6) | (1 << 20))  # bit 20: beyond the step, ignored
+    with pytest.raises(gpe.GpeError):
+        s.kernel_times(1, mask=1 << 9)
+    s.synchronize()
+    out = s.state()
+    assert s.diagnostics()["step"] == 9
+    s.close()
+    names = [r[0] for r in full]
+    assert len(names) == 7 and names == [r[0] for r in part] == [r[0] for r in ends]
+    assert all(r[1] > 0 for r in full)
+    assert [r[1] > 0 for r in part] == [q == 2 for q in range(7)]
+    assert [r[1] > 0 for r in ends] == [q in (0, 6) for q in range(7)]
+    assert [r[2] for r in part] == [r[2] for r in full] == [r[2] for r in ends]
+    for k in ("p", "u", "v", "w", "phi"):
+        assert np.array_equal(out[k], ref[k]), k
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("dim", [3, 2])
 def test_bitwise_across_z_chunks(gpe, dim, precision):
