@@ -59,59 +59,72 @@ __device__ __forceinline__ double wave_min(double v) {
 }
 
 // slots: 0 mass, 1 sum|phi|, 2 ke, 3 max|div|, 4 min phi (stored negated as
-// a max), 5 max phi, 6 max|u|, 7 non-finite count
+// a max), 5 max phi, 6 max|u|, 7 non-finite count.
+// Each wave takes whole grid rows (fixed j, k), rows strided over the launch:
+// the row's coordinates, weights and ghost-mapped neighbour rows along Y and
+// Z are wave-uniform, and the lanes stride along X (coalesced).
+constexpr int kDiagThreads = 512;
 template <typename T>
-__global__ __launch_bounds__(256) void diag_partial_kernel(DiagArgs<T> a) {
+__global__ __launch_bounds__(kDiagThreads) void diag_partial_kernel(DiagArgs<T> a) {
   const Grid& g = a.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const size_t ncell = (size_t)nx * ny * nz;
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY, 0.0, 0.0};
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
-       c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx);
-    const int j = (int)((c / nx) % ny);
-    const int k = (int)(c / ((size_t)nx * ny));
-    const double ph = (double)a.phi[c];
-    const double wr = a.axisym ? (k + 0.5) : 1.0;
-    acc[0] += wr * ph;
-    acc[1] += wr * fabs(ph);
-    acc[4] = fmax(acc[4], -ph);
-    acc[5] = fmax(acc[5], ph);
-    bool fin = isfinite(ph) && isfinite((double)a.q[0][c]);
-    const double rho_c = 0.5 * (a.rho_l * (1.0 + fmin(fmax(ph, -1.0), 1.0)) +
-                                a.rho_g * (1.0 - fmin(fmax(ph, -1.0), 1.0)));
-    double div = 0.0;
-    for (int ax = 0; ax < 3; ++ax) {
-      if (!a.q[1 + ax]) continue;
-      const double uf = (double)a.q[1 + ax][c];
-      fin = fin && isfinite(uf);
-      acc[6] = fmax(acc[6], fabs(uf));
-      // density at the low face: mean of the two adjacent cells
-      int idx[3] = {i, j, k};
-      idx[ax] -= 1;
-      int refl;
-      idx[ax] = map_cell(idx[ax], g.n[ax], g.bc[2 * ax], g.bc[2 * ax + 1], refl);
-      const double phl = (double)a.phi[((size_t)idx[2] * ny + idx[1]) * nx + idx[0]];
-      const double fl = fmin(fmax(phl, -1.0), 1.0);
-      const double rho_l = 0.5 * (a.rho_l * (1.0 + fl) + a.rho_g * (1.0 - fl));
-      const double rho_f = 0.5 * (rho_l + rho_c);
-      const double wf = (a.axisym && ax == 2) ? (double)k : wr;
-      acc[2] += 0.5 * rho_f * uf * uf * wf;
-      // high face value for the divergence
-      int hi[3] = {i, j, k};
-      int sgn;
-      hi[ax] = map_face(hi[ax] + 1, g.n[ax], g.bc[2 * ax], sgn);
-      const double uh = sgn * (double)a.q[1 + ax][((size_t)hi[2] * ny + hi[1]) * nx + hi[0]];
-      if (a.axisym && ax == 2)
-        div += ((k + 1.0) * uh - (double)k * uf) / (k + 0.5);
-      else
-        div += uh - uf;
-    }
-    acc[3] = fmax(acc[3], fabs(div));
-    if (!fin) acc[7] += 1.0;
-  }
-  __shared__ double red[4][8];
+  constexpr int NW = kDiagThreads / 64;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const size_t plane = (size_t)nx * ny;
+  const T* const uax[3] = {a.q[1], a.q[2], a.q[3]};
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY, 0.0, 0.0};
+  const int nrow = ny * nz;
+  for (int row = blockIdx.x * NW + wv; row < nrow; row += gridDim.x * NW) {
+    const int j = row % ny, k = row / ny;
+    const double wr = a.axisym ? (k + 0.5) : 1.0;
+    const size_t own = (size_t)k * plane + (size_t)j * nx;
+    // per axis: offset of the row holding the low neighbour cell (density at
+    // the low face) and of the row holding the high face, with that face's
+    // sign; along X both are the own row (the lane maps i itself)
+    int refl, sy = 1, sz = 1;
+    const size_t lo_row[3] = {own, (size_t)k * plane + (size_t)map_cell(j - 1, ny, g.bc[2], g.bc[3], refl) * nx,
+                              (size_t)map_cell(k - 1, nz, g.bc[4], g.bc[5], refl) * plane + (size_t)j * nx};
+    const size_t hi_row[3] = {own, (size_t)k * plane + (size_t)map_face(j + 1, ny, g.bc[2], sy) * nx,
+                              (size_t)map_face(k + 1, nz, g.bc[4], sz) * plane + (size_t)j * nx};
+    const double hi_sign[3] = {1.0, (double)sy, (double)sz};
+    for (int i = lane; i < nx; i += 64) {
+      const size_t c = own + i;
+      const double ph = (double)a.phi[c];
+      acc[0] += wr * ph;
+      acc[1] += wr * fabs(ph);
+      acc[4] = fmax(acc[4], -ph);
+      acc[5] = fmax(acc[5], ph);
+      bool fin = isfinite(ph) && isfinite((double)a.q[0][c]);
+      const double rho_c = 0.5 * (a.rho_l * (1.0 + fmin(fmax(ph, -1.0), 1.0)) +
+                                  a.rho_g * (1.0 - fmin(fmax(ph, -1.0), 1.0)));
+      int sx = 1;
+      const int il = map_cell(i - 1, nx, g.bc[0], g.bc[1], refl);
+      const int ih = map_face(i + 1, nx, g.bc[0], sx);
+      double div = 0.0;
+      for (int ax = 0; ax < 3; ++ax) {
+        if (!uax[ax]) continue;
+        const double uf = (double)uax[ax][c];
+        fin = fin && isfinite(uf);
+        acc[6] = fmax(acc[6], fabs(uf));
+        // density at the low face: mean of the two adjacent cells
+        const double phl = (double)a.phi[lo_row[ax] + (ax == 0 ? il : i)];
+        const double fl = fmin(fmax(phl, -1.0), 1.0);
+        const double rho_l = 0.5 * (a.rho_l * (1.0 + fl) + a.rho_g * (1.0 - fl));
+        const double rho_f = 0.5 * (rho_l + rho_c);
+        const double wf = (a.axisym && ax == 2) ? (double)k : wr;
+        acc[2] += 0.5 * rho_f * uf * uf * wf;
+        // high face value for the divergence
+        const double uh = (ax == 0 ? (double)sx : hi_sign[ax]) * (double)uax[ax][hi_row[ax] + (ax == 0 ? ih : i)];
+        if (a.axisym && ax == 2)
+          div += ((k + 1.0) * uh - (double)k * uf) / (k + 0.5);
+        else
+          div += uh - uf;
+      }
+      acc[3] = fmax(acc[3], fabs(div));
+      if (!fin) acc[7] += 1.0;
+    }
+  }
+  __shared__ double red[NW][8];
   double r[8];
   r[0] = wave_sum(acc[0]); r[1] = wave_sum(acc[1]); r[2] = wave_sum(acc[2]);
   r[3] = wave_max(acc[3]); r[4] = wave_max(acc[4]); r[5] = wave_max(acc[5]);
@@ -122,7 +135,7 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(DiagArgs<T> a) {
   if (threadIdx.x == 0) {
     double o[8];
     for (int s = 0; s < 8; ++s) o[s] = red[0][s];
-    for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
+    for (int w = 1; w < NW; ++w) {
       o[0] += red[w][0]; o[1] += red[w][1]; o[2] += red[w][2];
       o[3] = fmax(o[3], red[w][3]); o[4] = fmax(o[4], red[w][4]);
       o[5] = fmax(o[5], red[w][5]); o[6] = fmax(o[6], red[w][6]);
@@ -330,7 +343,7 @@ hipError_t launch_init(const InitArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_diag(const DiagArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((diag_partial_kernel<T>), dim3(kDiagBlocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((diag_partial_kernel<T>), dim3(kDiagBlocks), dim3(kDiagThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, a.partial, kDiagBlocks, a.result);
