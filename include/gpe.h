@@ -13,8 +13,13 @@
  * Conventions shared by every call:
  *  - Lattice units: grid spacing dx = 1.  dt and cs2 are free parameters
  *    (the paper fixes cs = dx / (sqrt(3) dt), Sec. 2, general pressure eq.).
- *  - Layout: every field is a dense array of shape (nz, ny, nx), x fastest
- *    (nz = 1 in 2-D).  Velocity components are stored on the LOW face of
+ *  - Layout: every field has the cells of shape (nz, ny, nx), x fastest
+ *    (nz = 1 in 2-D).  Host arrays (gpe_copy_field, the initial fields) are
+ *    dense.  On the device each x row is padded to gpe_field_pitch elements
+ *    (nx rounded up to a multiple of 64 when nx >= 64; nx itself below), so
+ *    row j of plane k starts at element (k ny + j) pitch and, from 64 cells
+ *    on, every row starts on a 256-byte boundary; the padding is zero and is
+ *    never read.  Velocity components are stored on the LOW face of
  *    their cell: u[k][j][i] sits between cells i-1 and i (Sec. 3, index
  *    convention of the divergence stencil).  For walls and symmetry planes
  *    the boundary-normal face of cell 0 is on the boundary and is always 0.
@@ -283,9 +288,9 @@ int gpe_interface_extent(gpe_state* s, double out[6]);
  * index outside the grid. */
 int gpe_line_crossings(gpe_state* s, int32_t axis, int32_t i0, int32_t i1, double out[2]);
 
-/* Copy one field between the device state and a host array of
+/* Copy one field between the device state and a dense host array of
  * n[0]*n[1]*n[2] doubles (converted from/to the state precision), in the
- * layout above.  GPE_FIELD_W is valid in 3-D only; for walls and symmetry
+ * layout above (the device rows are padded, the host rows are not).  GPE_FIELD_W is valid in 3-D only; for walls and symmetry
  * planes the boundary-normal faces written by GPE_H2D must be 0.
  * bytes must equal n[0]*n[1]*n[2]*8.  Synchronous. */
 int gpe_copy_field(gpe_state* s, int field, int dir, void* host, size_t bytes);
@@ -298,6 +303,14 @@ size_t gpe_field_offset(const gpe_state* s, int field);
  * as the workspace plus gpe_field_offset), or NULL for an invalid field.
  * For callers that run their own kernels on the fields. */
 void* gpe_field_pointer(const gpe_state* s, int field);
+
+/* Elements from one x row of a device field to the next (layout above):
+ * n[0] rounded up to a multiple of 64 when n[0] >= 64, else n[0]; or
+ * GPE_EINVAL for a null handle.
+ * Callers that address the fields themselves (gpe_field_pointer) use it as
+ * the row stride; a plane holds n[1] such rows (1 in 2-D, where the rows
+ * are the y lines). */
+int64_t gpe_field_pitch(const gpe_state* s);
 
 /* Overwrite the step counter and time (checkpoint restart). */
 int gpe_set_step_time(gpe_state* s, int64_t step, double t);

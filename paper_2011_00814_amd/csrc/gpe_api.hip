@@ -52,9 +52,11 @@ int validate(const gpe_params* p) {
   }
   const double ncell = (double)p->n[0] * p->n[1] * p->n[2];
   if (ncell > 4.0e9) return GPE_EINVAL;
-  // one Z plane (X x Y in the internal axis order) must stay below 2^32 bytes
+  // one Z plane (X x Y in the internal axis order, rows padded to the row
+  // pitch) must stay below 2^32 bytes
   const double esize = p->precision == GPE_FP64 ? 8.0 : 4.0;
-  const double plane = dim == 3 ? (double)p->n[0] * p->n[1] : (double)p->n[0];
+  const double pitch = (double)row_pitch(p);
+  const double plane = dim == 3 ? pitch * p->n[1] : pitch;
   if (plane * esize >= 4294967296.0) return GPE_EINVAL;
   for (int a = 0; a < dim; ++a) {
     const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
@@ -275,26 +277,35 @@ int field_buf(const gpe_state* s, int field) {
   return -1;
 }
 
+// Host array of the cells in the a0 order (rows of nx) <-> the padded rows
+// of a field buffer.
+hipError_t copy_rows(gpe_state* s, void* dev, void* host, size_t esize, int dir) {
+  const size_t nx = (size_t)s->grid.n[0], rows = s->ncell / nx, pitch = (size_t)s->grid.pitch;
+  if (pitch == nx)
+    return dir == GPE_H2D ? hipMemcpyAsync(dev, host, s->ncell * esize, hipMemcpyHostToDevice, s->stream)
+                          : hipMemcpyAsync(host, dev, s->ncell * esize, hipMemcpyDeviceToHost, s->stream);
+  return dir == GPE_H2D
+             ? hipMemcpy2DAsync(dev, pitch * esize, host, nx * esize, nx * esize, rows, hipMemcpyHostToDevice, s->stream)
+             : hipMemcpy2DAsync(host, nx * esize, dev, pitch * esize, nx * esize, rows, hipMemcpyDeviceToHost,
+                                s->stream);
+}
+
 template <typename T>
 int copy_t(gpe_state* s, int b, int dir, double* host) {
   T* dev = buf<T>(s, b);
   const size_t n = s->ncell;
   if (sizeof(T) == sizeof(double)) {
-    hipError_t e = dir == GPE_H2D
-                       ? hipMemcpyAsync(dev, host, n * sizeof(T), hipMemcpyHostToDevice, s->stream)
-                       : hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, s->stream);
-    if (e != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) return GPE_EHIP;
+    if (copy_rows(s, dev, host, sizeof(T), dir) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
+      return GPE_EHIP;
     return GPE_OK;
   }
   std::vector<T> tmp(n);
   if (dir == GPE_H2D) {
     for (size_t c = 0; c < n; ++c) tmp[c] = T(host[c]);
-    if (hipMemcpyAsync(dev, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
+    if (copy_rows(s, dev, tmp.data(), sizeof(T), dir) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
       return GPE_EHIP;
   } else {
-    if (hipMemcpyAsync(tmp.data(), dev, n * sizeof(T), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
+    if (copy_rows(s, dev, tmp.data(), sizeof(T), dir) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
       return GPE_EHIP;
     for (size_t c = 0; c < n; ++c) host[c] = (double)tmp[c];
   }
@@ -306,6 +317,7 @@ int init_fields_t(gpe_state* s, const double* h_phi0, const double* h_p0) {
   const gpe_params& P = s->P;
   gpe::InitArgs<T> a;
   for (int q = 0; q < 3; ++q) a.n[q] = s->grid.n[q];
+  a.pitch = s->grid.pitch;
   a.kind = h_phi0 ? 0 : P.init_kind;
   a.has_y = s->dim == 3;
   if (s->dim == 3) {
@@ -505,12 +517,12 @@ int gpe_params_from_dimensionless(const gpe_problem* in, gpe_params* out) {
 size_t gpe_workspace_bytes(const gpe_params* p) {
   if (validate(p) != GPE_OK) return 0;
   const size_t esize = p->precision == GPE_FP64 ? 8 : 4;
-  const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+  const size_t fcell = field_elems(p);
   bool need[B_COUNT];
   needed(p, need);
   size_t total = 0;
   for (int b = 0; b < B_SCR; ++b)
-    if (need[b]) total += align_up(ncell * esize);
+    if (need[b]) total += align_up(fcell * esize);
   total += align_up(scratch_bytes());
   return total;
 }
@@ -532,6 +544,7 @@ int gpe_init_state(const gpe_params* p, void* d_workspace, size_t bytes, void* h
   s->axi = p->geometry == GPE_GEOM_AXISYM;
   s->esize = p->precision == GPE_FP64 ? 8 : 4;
   s->ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+  s->fcell = field_elems(p);
   s->stream = (hipStream_t)hip_stream;
   s->ws = (char*)d_workspace;
   s->ws_bytes = bytes;
@@ -553,6 +566,7 @@ int gpe_init_state(const gpe_params* p, void* d_workspace, size_t bytes, void* h
     s->grid.bc[4] = p->bc[2];
     s->grid.bc[5] = p->bc[3];
   }
+  s->grid.pitch = (int)row_pitch(p);
   s->grid.zchunk = 1;
   {
     int dev = 0, ncu = 0;
@@ -568,14 +582,16 @@ int gpe_init_state(const gpe_params* p, void* d_workspace, size_t bytes, void* h
   for (int b = 0; b < B_SCR; ++b) {
     if (need[b]) {
       s->off[b] = o;
-      o += align_up(s->ncell * s->esize);
+      o += align_up(s->fcell * s->esize);
     } else {
       s->off[b] = (size_t)-1;
     }
   }
   s->off[B_SCR] = o;
-  int r = p->precision == GPE_FP64 ? init_fields_t<double>(s, h_phi0, h_p0)
-                                   : init_fields_t<float>(s, h_phi0, h_p0);
+  // every field buffer starts at zero, the row padding included
+  int r = hipMemsetAsync(s->ws, 0, o, s->stream) == hipSuccess ? GPE_OK : GPE_EHIP;
+  if (!r)
+    r = p->precision == GPE_FP64 ? init_fields_t<double>(s, h_phi0, h_p0) : init_fields_t<float>(s, h_phi0, h_p0);
   double d[8];
   if (!r) r = run_diag(s, d);
   if (r) {
@@ -661,6 +677,8 @@ void* gpe_field_pointer(const gpe_state* s, int field) {
   const int b = field_buf(s, field);
   return b < 0 ? nullptr : (void*)(s->ws + s->off[b]);
 }
+
+int64_t gpe_field_pitch(const gpe_state* s) { return s ? (int64_t)s->grid.pitch : GPE_EINVAL; }
 
 int gpe_set_step_time(gpe_state* s, int64_t step, double t) {
   if (!s || step < 0) return GPE_EINVAL;

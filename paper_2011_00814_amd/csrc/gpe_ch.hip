@@ -53,7 +53,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
 
   const Grid& g = A.g;
   const Consts<T>& c = A.c;
-  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2], pitch = g.pitch;
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = btx * TX, y0 = bty * TY;
   const int z0 = btz * g.zchunk;
@@ -61,7 +61,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
-  const int ij = j * nx + i;  // in-plane offset of the own column
+  const int ij = j * pitch + i;  // in-plane offset of the own column
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
   const T* const L0 = lds + own;
   const T* const Q0 = ldq + ((DIM == 3) ? (ty + 1) * QX : 0) + tx + 1;
@@ -207,7 +207,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   // value of the chunk that is never used)
   uint32_t bo_own = (uint32_t)(active ? ij : 0) * (uint32_t)sizeof(T);
   auto fetch_pt = [&](int k, T& ps, T& ac) {
-    const size_t po = (size_t)min(max(k, z0), z1 - 1) * ny * nx;
+    const size_t po = (size_t)min(max(k, z0), z1 - 1) * ny * pitch;
     refresh(bo_own);
     if (NEED_PHIS) ps = ld_nt(A.phis + po, bo_own);
     if (NEED_ACC) ac = ld_nt(A.acc + po, bo_own);
@@ -224,7 +224,7 @@ __device__ __forceinline__ void ch_stage_tile(const ChArgs<T>& A, int btx, int b
   constexpr bool WRITES_ACC = STAGE == CH_RK2_1 || STAGE == CH_RK4_1 || STAGE == CH_RK4_2 || STAGE == CH_RK4_3;
   auto store = [&](int k) {
     if (k >= z0 && active) {
-      const size_t po = (size_t)k * ny * nx;
+      const size_t po = (size_t)k * ny * pitch;
       st_nt(A.out + po, bo_own, pv_out);
       if (WRITES_ACC) st_nt(A.acc + po, bo_own, pv_acc);
     }

@@ -202,7 +202,7 @@ int upload_tables(gpe_ensemble* e) {
     fields[4 * (size_t)i + 1] = buf<T>(s, B_Q0 + 1);
     fields[4 * (size_t)i + 2] = buf<T>(s, B_Q0 + 3);
     fields[4 * (size_t)i + 3] = buf<T>(s, B_PHI);
-    ncell[i] = (int64_t)s->ncell;
+    ncell[i] = (int64_t)s->fcell;  // whole buffers: the row padding is zero
   }
   if ((int)ft.size() > e->L.max_flow_tiles || (int)ct.size() > e->L.max_ch_tiles) return GPE_EINVAL;
   e->nflow_tiles = (int)ft.size();

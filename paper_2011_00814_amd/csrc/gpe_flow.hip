@@ -64,7 +64,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
 
   const Grid& g = A.g;
   const Consts<T>& c = A.c;
-  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2], pitch = g.pitch;
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = btx * TX, y0 = bty * TY;
   const int z0 = btz * g.zchunk;
@@ -72,7 +72,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   const int z1 = min(z0 + g.zchunk, nz);
   const int i = x0 + tx, j = (DIM == 3) ? y0 + ty : 0;
   const bool active = i < nx && j < ny;
-  const int ij = j * nx + i;  // in-plane offset of the own column
+  const int ij = j * pitch + i;  // in-plane offset of the own column
   const int own = ((DIM == 3) ? (ty + 2) * PX : 0) + tx + 2;
   T* const L0 = lds + own;  // LDS base of the thread's own column
 
@@ -105,7 +105,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
     const auto q = pm.pos(g, p);
     const bool ok = pm.ok[p];
     const int oc = ok ? q.oc : 0;
-    const int dq = (DIM == 3 && pm.interior && !pm.inner_row(p)) ? nx : 0;
+    const int dq = (DIM == 3 && pm.interior && !pm.inner_row(p)) ? pitch : 0;
     bo_f[p] = (uint32_t)oc * (uint32_t)sizeof(T);
     bo_c[p] = (uint32_t)(oc + dq) * (uint32_t)sizeof(T);
     bo_x[p] = (uint32_t)((ok ? q.ox : 0) + dq) * (uint32_t)sizeof(T);
@@ -291,7 +291,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
   auto fetch_qn = [&](int k, T* dst) {
     refresh(bo_own);
     if (STAGE >= 2) {  // an inactive lane loads the plane's first element (unused)
-      const size_t pk = (size_t)k * ny * nx;
+      const size_t pk = (size_t)k * ny * pitch;
 #pragma unroll
       for (int f = 0; f < 4; ++f)
         if (DIM == 3 || f != 2) dst[f] = ld_nt((STAGE == 3 ? A.dst[f] : A.qn[f]) + pk, bo_own);
@@ -491,7 +491,7 @@ __device__ __forceinline__ void flow_stage_tile(const FlowArgs<T>& A, int btx, i
       if (bX) out[1] = T(0);
       if (bY) out[2] = T(0);
       if (bZ) out[3] = T(0);
-      const size_t pk = (size_t)k * ny * nx;
+      const size_t pk = (size_t)k * ny * pitch;
       st_nt(A.dst[0] + pk, bo_own, out[0]);
       st_nt(A.dst[1] + pk, bo_own, out[1]);
       if (DIM == 3) st_nt(A.dst[2] + pk, bo_own, out[2]);

@@ -28,8 +28,22 @@ enum Buf {
 };
 
 constexpr size_t kAlign = 256;
+constexpr size_t kRowAlign = 64;  // elements: every X row of a field starts on a 256-byte boundary
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Elements from one X row of a field to the next: the X extent rounded up to
+// a multiple of kRowAlign (the padding is zero and never read); a grid
+// narrower than kRowAlign keeps dense rows (a row then spans a cache line or
+// two whatever its alignment).
+inline size_t row_pitch(const gpe_params* p) {
+  const size_t nx = (size_t)p->n[0];
+  return nx < kRowAlign ? nx : (nx + kRowAlign - 1) / kRowAlign * kRowAlign;
+}
+
+// Elements of one field buffer: rows of row_pitch for every (Y, Z) (2-D:
+// every physical y; n[2] is 1 there).
+inline size_t field_elems(const gpe_params* p) { return row_pitch(p) * (size_t)p->n[1] * (size_t)p->n[2]; }
 
 }  // namespace gpe_host
 
@@ -38,7 +52,8 @@ struct gpe_state {
   int dim;                 // 2 or 3
   bool axi;
   size_t esize;            // bytes per element
-  size_t ncell;
+  size_t ncell;            // cells of the grid
+  size_t fcell;            // elements of one field buffer (rows padded to grid.pitch)
   gpe::Grid grid;          // internal
   hipStream_t stream;
   char* ws;

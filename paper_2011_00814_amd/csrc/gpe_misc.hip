@@ -14,6 +14,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
     const int i = (int)(c % a.n[0]);
     const int j = (int)((c / a.n[0]) % a.n[1]);
     const int k = (int)(c / ((size_t)a.n[0] * a.n[1]));
+    const size_t at = ((size_t)k * a.n[1] + j) * a.pitch + i;  // element of cell (i, j, k)
     const double x = i + 0.5, y = j + 0.5, z = k + 0.5;
     double ph = a.amp;
     if (a.kind == 1 || a.kind == 2) {
@@ -39,9 +40,9 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
       }
       ph = tanh(2.0 * a.radius * (1.0 - sqrt(rr)) / a.width);
     }
-    a.phi[c] = T(ph);
+    a.phi[at] = T(ph);
     for (int f = 0; f < 4; ++f)
-      if (a.q[f]) a.q[f][c] = T(0);
+      if (a.q[f]) a.q[f][at] = T(0);
   }
 }
 
@@ -70,22 +71,22 @@ __global__ __launch_bounds__(kDiagThreads) void diag_partial_kernel(DiagArgs<T> 
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   constexpr int NW = kDiagThreads / 64;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  const size_t plane = (size_t)nx * ny;
+  const size_t pitch = (size_t)g.pitch, plane = pitch * ny;
   const T* const uax[3] = {a.q[1], a.q[2], a.q[3]};
   double acc[8] = {0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY, 0.0, 0.0};
   const int nrow = ny * nz;
   for (int row = blockIdx.x * NW + wv; row < nrow; row += gridDim.x * NW) {
     const int j = row % ny, k = row / ny;
     const double wr = a.axisym ? (k + 0.5) : 1.0;
-    const size_t own = (size_t)k * plane + (size_t)j * nx;
+    const size_t own = (size_t)k * plane + (size_t)j * pitch;
     // per axis: offset of the row holding the low neighbour cell (density at
     // the low face) and of the row holding the high face, with that face's
     // sign; along X both are the own row (the lane maps i itself)
     int refl, sy = 1, sz = 1;
-    const size_t lo_row[3] = {own, (size_t)k * plane + (size_t)map_cell(j - 1, ny, g.bc[2], g.bc[3], refl) * nx,
-                              (size_t)map_cell(k - 1, nz, g.bc[4], g.bc[5], refl) * plane + (size_t)j * nx};
-    const size_t hi_row[3] = {own, (size_t)k * plane + (size_t)map_face(j + 1, ny, g.bc[2], sy) * nx,
-                              (size_t)map_face(k + 1, nz, g.bc[4], sz) * plane + (size_t)j * nx};
+    const size_t lo_row[3] = {own, (size_t)k * plane + (size_t)map_cell(j - 1, ny, g.bc[2], g.bc[3], refl) * pitch,
+                              (size_t)map_cell(k - 1, nz, g.bc[4], g.bc[5], refl) * plane + (size_t)j * pitch};
+    const size_t hi_row[3] = {own, (size_t)k * plane + (size_t)map_face(j + 1, ny, g.bc[2], sy) * pitch,
+                              (size_t)map_face(k + 1, nz, g.bc[4], sz) * plane + (size_t)j * pitch};
     const double hi_sign[3] = {1.0, (double)sy, (double)sz};
     for (int i = lane; i < nx; i += 64) {
       const size_t c = own + i;
@@ -174,12 +175,13 @@ __global__ __launch_bounds__(64) void diag_final_kernel(const double* partial, i
 // high faces, the high face by the ghost rule of the boundary it may lie on
 template <typename T>
 __device__ __forceinline__ double centre_velocity(const Grid& g, const T* u, int ax, int i, int j, int k) {
-  const int nx = g.n[0], ny = g.n[1];
-  const double lo = (double)u[((size_t)k * ny + j) * nx + i];
+  const int ny = g.n[1];
+  const size_t pitch = (size_t)g.pitch;
+  const double lo = (double)u[((size_t)k * ny + j) * pitch + i];
   int hi[3] = {i, j, k};
   int sgn;
   hi[ax] = map_face(hi[ax] + 1, g.n[ax], g.bc[2 * ax], sgn);
-  const double up = sgn * (double)u[((size_t)hi[2] * ny + hi[1]) * nx + hi[0]];
+  const double up = sgn * (double)u[((size_t)hi[2] * ny + hi[1]) * pitch + hi[0]];
   return 0.5 * (lo + up);
 }
 
@@ -193,10 +195,10 @@ __global__ __launch_bounds__(256) void phase_stats_kernel(PhaseArgs<T> a) {
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (size_t)gridDim.x * blockDim.x) {
-    if (!((double)a.phi[c] > 0.0)) continue;
     const int i = (int)(c % nx);
     const int j = (int)((c / nx) % ny);
     const int k = (int)(c / ((size_t)nx * ny));
+    if (!((double)a.phi[((size_t)k * ny + j) * g.pitch + i] > 0.0)) continue;
     const double w = a.axisym ? (k + 0.5) : 1.0;
     acc[0] += w;
     acc[1] += w * (i + 0.5);
@@ -248,16 +250,17 @@ __global__ __launch_bounds__(256) void interface_extent_kernel(PhaseArgs<T> a) {
   const Grid& g = a.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const size_t ncell = (size_t)nx * ny * nz;
-  const size_t stride[3] = {1, (size_t)nx, (size_t)nx * ny};
+  const size_t stride[3] = {1, (size_t)g.pitch, (size_t)g.pitch * ny};
   double acc[6] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (size_t)gridDim.x * blockDim.x) {
     const int idx[3] = {(int)(c % nx), (int)((c / nx) % ny), (int)(c / ((size_t)nx * ny))};
-    const double f0 = (double)a.phi[c];
+    const size_t at = idx[0] + idx[1] * stride[1] + idx[2] * stride[2];
+    const double f0 = (double)a.phi[at];
     for (int ax = 0; ax < 3; ++ax) {
       if (idx[ax] + 1 >= g.n[ax]) continue;
       double pos;
-      if (crossing(f0, (double)a.phi[c + stride[ax]], idx[ax] + 0.5, pos)) {
+      if (crossing(f0, (double)a.phi[at + stride[ax]], idx[ax] + 0.5, pos)) {
         acc[2 * ax] = fmax(acc[2 * ax], -pos);
         acc[2 * ax + 1] = fmax(acc[2 * ax + 1], pos);
       }
@@ -300,7 +303,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void line_crossings_kernel(PhaseArgs<T> a) {
   const Grid& g = a.g;
   const int ax = a.axis, n = g.n[ax];
-  const size_t stride[3] = {1, (size_t)g.n[0], (size_t)g.n[0] * g.n[1]};
+  const size_t stride[3] = {1, (size_t)g.pitch, (size_t)g.pitch * g.n[1]};
   size_t base = 0;
   for (int d = 0; d < 3; ++d)
     if (d != ax) base += (size_t)a.idx[d] * stride[d];

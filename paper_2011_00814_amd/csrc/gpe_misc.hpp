@@ -13,6 +13,7 @@ constexpr int kDiagBlocks = 512;
 template <typename T>
 struct InitArgs {
   int n[3];          // internal X, Y, Z sizes
+  int pitch;         // elements per X row of a field (>= n[0])
   int kind;          // gpe_init_kind
   int has_y;         // 3-D: include the Y distance
   double center[3];  // internal axis order

@@ -35,7 +35,7 @@ struct PlaneMap {
   __device__ __forceinline__ void init(const Grid& g, int x0_, int y0_) {
     x0 = x0_;
     y0 = y0_;
-    const int nx = g.n[0], ny = g.n[1];
+    const int nx = g.n[0], ny = g.n[1], pitch = g.pitch;
     interior = x0 - 2 >= 0 && x0 - 2 + PX - 1 <= nx - 1;
     if (DIM == 3) interior = interior && y0 - 2 >= 0 && y0 - 2 + PY - 1 <= ny - 1;
 #pragma unroll
@@ -45,7 +45,7 @@ struct PlaneMap {
       // bits 0-7: X-face delta + 128, 8-15: Y-face delta in rows + 128,
       // 16-17 / 18-19 / 20-21: sx / sy / sz + 1
       const int dx = q.sx != T(0) ? q.ox - q.oc : 0;
-      const int dy = q.sy != T(0) ? (q.oy - q.oc) / nx : 0;
+      const int dy = q.sy != T(0) ? (q.oy - q.oc) / pitch : 0;
       pk[p] = (dx + 128) | ((dy + 128) << 8) | ((int)q.sx + 1) << 16 | ((int)q.sy + 1) << 18 |
               ((int)q.sz + 1) << 20;
     }
@@ -72,9 +72,9 @@ struct PlaneMap {
     }
     const int wx = (rx == BC_WALL) ? -1 : 1;
     const int wy = (ry == BC_WALL) ? -1 : 1;
-    q.oc = my * nx + mx;
-    q.ox = my * nx + fx;
-    q.oy = fy * nx + mx;
+    q.oc = my * g.pitch + mx;
+    q.ox = my * g.pitch + fx;
+    q.oy = fy * g.pitch + mx;
     q.sx = T(fxs * wy);
     q.sy = T(fys * wx);
     q.sz = T(wx * wy);
@@ -94,7 +94,7 @@ struct PlaneMap {
     if (interior) return Pos{off_c[p], off_c[p], off_c[p], T(1), T(1), T(1)};
     const int w = pk[p], oc = off_c[p];
     const int dx = (w & 255) - 128, dy = ((w >> 8) & 255) - 128;
-    return Pos{oc, oc + dx, oc + dy * g.n[0], T(((w >> 16) & 3) - 1), T(((w >> 18) & 3) - 1),
+    return Pos{oc, oc + dx, oc + dy * g.pitch, T(((w >> 16) & 3) - 1), T(((w >> 18) & 3) - 1),
                T(((w >> 20) & 3) - 1)};
   }
 };
@@ -110,7 +110,7 @@ struct ZMap {
     int rz, fzs;
     const int mz = map_cell(k, g.n[2], g.bc[4], g.bc[5], rz);
     const int fz = map_face(k, g.n[2], g.bc[4], fzs);
-    const size_t pl = (size_t)g.n[0] * g.n[1];
+    const size_t pl = (size_t)g.pitch * g.n[1];
     zc = (size_t)mz * pl;
     zf = (size_t)fz * pl;
     tan = (rz == BC_WALL) ? T(-1) : T(1);

@@ -80,7 +80,7 @@ _lib = None
 def header_functions():
     """Names of the functions declared in include/gpe.h."""
     src = open(HEADER).read()
-    return re.findall(r"^\s*(?:int|size_t|void|void\*|const char\*|gpe_state\*)\s+(gpe_\w+)\s*\(", src, re.M)
+    return re.findall(r"^\s*(?:int|int64_t|size_t|void|void\*|const char\*|gpe_state\*)\s+(gpe_\w+)\s*\(", src, re.M)
 
 
 def lib():
@@ -120,6 +120,8 @@ def lib():
         L.gpe_field_offset.restype = sz
         L.gpe_field_pointer.argtypes = [vp, ctypes.c_int]
         L.gpe_field_pointer.restype = vp
+        L.gpe_field_pitch.argtypes = [vp]
+        L.gpe_field_pitch.restype = ctypes.c_int64
         L.gpe_set_step_time.argtypes = [vp, ctypes.c_int64, f64]
         L.gpe_set_step_time.restype = ctypes.c_int
         L.gpe_kernel_times.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
@@ -247,6 +249,13 @@ def gpe_field_pointer(h, field: int) -> int:
     if not p:
         raise GpeError(GPE_EINVAL, "gpe_field_pointer")
     return int(p)
+
+
+def gpe_field_pitch(h) -> int:
+    n = int(lib().gpe_field_pitch(h))
+    if n < 0:
+        raise GpeError(n, "gpe_field_pitch")
+    return n
 
 
 def gpe_set_step_time(h, step: int, t: float):

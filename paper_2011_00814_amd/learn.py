@@ -154,9 +154,14 @@ def pointer_table(ptrs, device):
 
 def state_pointers(grids):
     """(u, v, p, phi) device pointers of 2-D FP32 grid handles (Solver or
-    EnsembleCase objects): what the kernels of this module read and write."""
+    EnsembleCase objects): what the kernels of this module read and write.
+    Those kernels address a field as dense rows of nx, so the grids' device
+    rows must carry no padding (nx below 64 or a multiple of 64)."""
     out = []
     for g in grids:
+        nx = g.shape[-1]
+        if G.gpe_field_pitch(g.h) != nx:
+            raise ValueError(f"learned-correction kernels need unpadded rows: nx = {nx} has a row pitch")
         for f in (G.GPE_FIELD_U, G.GPE_FIELD_V, G.GPE_FIELD_P, G.GPE_FIELD_PHI):
             out.append(G.gpe_field_pointer(g.h, f))
     return out

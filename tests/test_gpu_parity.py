@@ -66,6 +66,8 @@ CASES = {
     "rt2d_walls": lambda: W.rayleigh_taylor_2d(nx=70, ny=150, amp_frac=0.05),
     "axisym_drop": lambda: W.axisym_drop(nz=100, nr=37, R=10.0, zc=45.0),
     "bubble3d_walls": lambda: W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0, precision="fp64"),
+    # 70 cells along x: rows padded to a pitch of 128 on the device
+    "bubble3d_wide": lambda: W.rising_bubble_3d(nx=70, ny=16, nz=24, R=5.0, zc=10.0, precision="fp64"),
 }
 
 
@@ -74,7 +76,7 @@ def _case(name, seed=1, precision="fp64"):
     prob = dict(prob, precision=precision)
     if name == "rt2d_walls":
         prob["g"] = (0.0, -2e-4, 0.0)
-    if name == "bubble3d_walls":
+    if name.startswith("bubble3d"):
         prob["Fr"] = 0.5  # g = U_c^2 / (Fr^2 D) = 2.6e-4 (sigma and eta_L follow from Eo and Mo)
     st = W.perturbed(prob, st, seed, uamp=2e-3, pamp=2e-4)
     return prob, st
@@ -250,6 +252,45 @@ def test_graph_replay_equals_eager_bitwise(gpe):
         for k in a:
             if a[k] is not None:
                 assert np.array_equal(a[k], b[k]), (name, k)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_padded_rows(gpe, precision):
+    """x rows of 64 cells or more are padded on the device to a multiple of
+    64 elements: the pitch query gives the stride, a host field makes the round trip through
+    the padded buffer unchanged, and after 20 steps the padding of every
+    state field still holds zeros (no kernel reads or writes it) while the
+    cells are finite."""
+    import torch
+
+    cases = [W.rising_bubble_3d(nx=70, ny=19, nz=45, R=7.0, zc=17.0, precision=precision),
+             W.rayleigh_taylor_2d(nx=70, ny=96, amp_frac=0.05, precision=precision)]
+    esz, dt = (8, torch.float64) if precision == "fp64" else (4, torch.float32)
+    for prob, st in cases:
+        st = W.perturbed(prob, st, 5, uamp=2e-3, pamp=2e-4)
+        nx = prob["n"][0]
+        _say(f"[pitch] {precision} n={prob['n']}")
+        s = gpe.Solver(prob, st)
+        pitch = gpe.gpe_field_pitch(s.h)
+        assert pitch == (nx + 63) // 64 * 64 and pitch > nx
+        want = np.asarray(st["phi"], dtype=np.float64).reshape(s.shape)
+        if precision == "fp32":
+            want = want.astype(np.float32).astype(np.float64)
+        assert np.array_equal(s.get("phi"), want)
+        s.run(20)
+        s.synchronize()
+        rows = int(np.prod(s.shape)) // nx
+        base = s.ws_ptr - s.ws.data_ptr()
+        fields = [gpe.GPE_FIELD_P, gpe.GPE_FIELD_U, gpe.GPE_FIELD_V, gpe.GPE_FIELD_PHI]
+        if prob["dim"] == 3:
+            fields.append(gpe.GPE_FIELD_W)
+        for f in fields:
+            off = base + gpe.gpe_field_offset(s.h, f)
+            buf = s.ws[off:off + rows * pitch * esz].view(dt).reshape(rows, pitch)
+            assert torch.count_nonzero(buf[:, nx:]).item() == 0, f
+            assert bool(torch.isfinite(buf[:, :nx]).all()), f
+        assert s.diagnostics()["finite"] == 1
+        s.close()
 
 
 def test_kernel_times_run_the_plain_steps(gpe):

@@ -22,7 +22,7 @@ def G():
 
 def test_exports_every_header_symbol(G):
     names = G.header_functions()
-    assert len(names) == 25
+    assert len(names) == 26
     L = G.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -183,6 +183,17 @@ def test_workspace_bytes(G):
     P3 = G.params_from_problem(prob3)
     n3 = 256 ** 3 * 4
     assert G.gpe_workspace_bytes(P3) == 19 * n3 + align((512 * 8 + 8) * 8)
+    # x rows padded to a multiple of 64 elements from 64 cells on: 70 -> 128,
+    # 130 -> 192; narrower grids keep dense rows (40)
+    prob4, _ = W.rising_bubble_3d(nx=130, ny=19, nz=45, R=7.0, zc=17.0, precision="fp32")
+    P4 = G.params_from_problem(prob4)
+    assert G.gpe_workspace_bytes(P4) == 19 * align(192 * 19 * 45 * 4) + align((512 * 8 + 8) * 8)
+    prob6, _ = W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0, precision="fp32")
+    P6 = G.params_from_problem(prob6)
+    assert G.gpe_workspace_bytes(P6) == 19 * align(40 * 19 * 45 * 4) + align((512 * 8 + 8) * 8)
+    prob5, _ = W.static_drop_2d(n=70)
+    P5 = G.params_from_problem(prob5)
+    assert G.gpe_workspace_bytes(P5) == 14 * align(128 * 70 * 8) + align((512 * 8 + 8) * 8)
 
 
 @pytest.mark.parametrize("mutate", [
