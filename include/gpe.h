@@ -15,11 +15,11 @@
  *    (the paper fixes cs = dx / (sqrt(3) dt), Sec. 2, general pressure eq.).
  *  - Layout: every field has the cells of shape (nz, ny, nx), x fastest
  *    (nz = 1 in 2-D).  Host arrays (gpe_copy_field, the initial fields) are
- *    dense.  On the device each x row is padded to gpe_field_pitch elements
- *    (nx rounded up to a multiple of 64 when nx >= 64; nx itself below), so
- *    row j of plane k starts at element (k ny + j) pitch and, from 64 cells
- *    on, every row starts on a 256-byte boundary; the padding is zero and is
- *    never read.  Velocity components are stored on the LOW face of
+ *    dense.  On the device each x row takes gpe_field_pitch elements: in
+ *    FP32 with nx >= 64, nx rounded up to a multiple of 64, so that every
+ *    row starts on a 256-byte boundary; otherwise nx.  Row j of plane k
+ *    starts at element (k ny + j) pitch; the padding is zero and is never
+ *    read.  Velocity components are stored on the LOW face of
  *    their cell: u[k][j][i] sits between cells i-1 and i (Sec. 3, index
  *    convention of the divergence stencil).  For walls and symmetry planes
  *    the boundary-normal face of cell 0 is on the boundary and is always 0.
@@ -305,8 +305,8 @@ size_t gpe_field_offset(const gpe_state* s, int field);
 void* gpe_field_pointer(const gpe_state* s, int field);
 
 /* Elements from one x row of a device field to the next (layout above):
- * n[0] rounded up to a multiple of 64 when n[0] >= 64, else n[0]; or
- * GPE_EINVAL for a null handle.
+ * in FP32 with n[0] >= 64, n[0] rounded up to a multiple of 64, else n[0];
+ * or GPE_EINVAL for a null handle.
  * Callers that address the fields themselves (gpe_field_pointer) use it as
  * the row stride; a plane holds n[1] such rows (1 in 2-D, where the rows
  * are the y lines). */

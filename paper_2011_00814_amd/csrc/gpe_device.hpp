@@ -17,9 +17,9 @@ enum { BC_PERIODIC = 0, BC_WALL = 1, BC_SYMMETRY = 2 };
 
 // Grid description in internal axis order.  A field is stored as Z planes
 // of Y rows; a row holds n[0] cells followed by unused padding up to pitch
-// elements (a multiple of 64 from 64 cells on, so every row starts on a
-// 256-byte boundary and the 32-column tile rows of the kernels cover whole
-// cache lines; narrower grids keep dense rows).
+// elements (FP32 from 64 cells on: a multiple of 64, so every row starts on
+// a 256-byte boundary and the 32-column tile rows of the kernels cover whole
+// cache lines; otherwise dense rows, pitch = n[0]).
 struct Grid {
   int n[3];    // cells along X, Y, Z (n[1] = 1 in 2-D)
   int pitch;   // elements from one X row to the next (>= n[0])

@@ -156,7 +156,7 @@ def state_pointers(grids):
     """(u, v, p, phi) device pointers of 2-D FP32 grid handles (Solver or
     EnsembleCase objects): what the kernels of this module read and write.
     Those kernels address a field as dense rows of nx, so the grids' device
-    rows must carry no padding (nx below 64 or a multiple of 64)."""
+    rows must carry no padding (FP32: nx below 64 or a multiple of 64)."""
     out = []
     for g in grids:
         nx = g.shape[-1]

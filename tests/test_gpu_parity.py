@@ -66,7 +66,7 @@ CASES = {
     "rt2d_walls": lambda: W.rayleigh_taylor_2d(nx=70, ny=150, amp_frac=0.05),
     "axisym_drop": lambda: W.axisym_drop(nz=100, nr=37, R=10.0, zc=45.0),
     "bubble3d_walls": lambda: W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0, precision="fp64"),
-    # 70 cells along x: rows padded to a pitch of 128 on the device
+    # 70 cells along x: in FP32 the rows are padded to a pitch of 128 on the device
     "bubble3d_wide": lambda: W.rising_bubble_3d(nx=70, ny=16, nz=24, R=5.0, zc=10.0, precision="fp64"),
 }
 
@@ -256,8 +256,9 @@ def test_graph_replay_equals_eager_bitwise(gpe):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_padded_rows(gpe, precision):
-    """x rows of 64 cells or more are padded on the device to a multiple of
-    64 elements: the pitch query gives the stride, a host field makes the round trip through
+    """FP32 x rows of 64 cells or more are padded on the device to a
+    multiple of 64 elements (FP64 rows stay dense): the pitch query gives the
+    stride, a host field makes the round trip through
     the padded buffer unchanged, and after 20 steps the padding of every
     state field still holds zeros (no kernel reads or writes it) while the
     cells are finite."""
@@ -272,7 +273,7 @@ def test_padded_rows(gpe, precision):
         _say(f"[pitch] {precision} n={prob['n']}")
         s = gpe.Solver(prob, st)
         pitch = gpe.gpe_field_pitch(s.h)
-        assert pitch == (nx + 63) // 64 * 64 and pitch > nx
+        assert pitch == ((nx + 63) // 64 * 64 if precision == "fp32" else nx)
         want = np.asarray(st["phi"], dtype=np.float64).reshape(s.shape)
         if precision == "fp32":
             want = want.astype(np.float32).astype(np.float64)

@@ -183,17 +183,20 @@ def test_workspace_bytes(G):
     P3 = G.params_from_problem(prob3)
     n3 = 256 ** 3 * 4
     assert G.gpe_workspace_bytes(P3) == 19 * n3 + align((512 * 8 + 8) * 8)
-    # x rows padded to a multiple of 64 elements from 64 cells on: 70 -> 128,
-    # 130 -> 192; narrower grids keep dense rows (40)
+    # FP32 x rows padded to a multiple of 64 elements from 64 cells on:
+    # 130 -> 192, 70 -> 128; narrower grids (40) and FP64 keep dense rows
     prob4, _ = W.rising_bubble_3d(nx=130, ny=19, nz=45, R=7.0, zc=17.0, precision="fp32")
     P4 = G.params_from_problem(prob4)
     assert G.gpe_workspace_bytes(P4) == 19 * align(192 * 19 * 45 * 4) + align((512 * 8 + 8) * 8)
     prob6, _ = W.rising_bubble_3d(nx=40, ny=19, nz=45, R=7.0, zc=17.0, precision="fp32")
     P6 = G.params_from_problem(prob6)
     assert G.gpe_workspace_bytes(P6) == 19 * align(40 * 19 * 45 * 4) + align((512 * 8 + 8) * 8)
-    prob5, _ = W.static_drop_2d(n=70)
+    prob5, _ = W.static_drop_2d(n=70, precision="fp32")
     P5 = G.params_from_problem(prob5)
-    assert G.gpe_workspace_bytes(P5) == 14 * align(128 * 70 * 8) + align((512 * 8 + 8) * 8)
+    assert G.gpe_workspace_bytes(P5) == 14 * align(128 * 70 * 4) + align((512 * 8 + 8) * 8)
+    prob7, _ = W.static_drop_2d(n=70, precision="fp64")
+    P7 = G.params_from_problem(prob7)
+    assert G.gpe_workspace_bytes(P7) == 14 * align(70 * 70 * 8) + align((512 * 8 + 8) * 8)
 
 
 @pytest.mark.parametrize("mutate", [
