@@ -116,10 +116,11 @@ __global__ __launch_bounds__(kBlock) void features_kernel(const float* const* fi
   const float uc = 0.5f * (u[o] + u[(size_t)y * W + wrap(x + 1, W)]);
   const float vn = (y + 1 < H) ? v[o + W] : 0.f;  // the face above the top row is a wall face
   const float vc = 0.5f * (v[o] + vn);
-  store(x0[q * 4 + 0], uc / s0);
-  store(x0[q * 4 + 1], vc / s1);
-  store(x0[q * 4 + 2], p[o] / s2);
-  store(x0[q * 4 + 3], ph[o] / s3);
+  // scaled by the reciprocals of the scales (as the fused inference does)
+  store(x0[q * 4 + 0], uc * (1.f / s0));
+  store(x0[q * 4 + 1], vc * (1.f / s1));
+  store(x0[q * 4 + 2], p[o] * (1.f / s2));
+  store(x0[q * 4 + 3], ph[o] * (1.f / s3));
 }
 
 __global__ __launch_bounds__(kBlock) void target_kernel(const float* const* next, const float* const* pred, int B,
@@ -251,9 +252,13 @@ __global__ __launch_bounds__(kBlock) void conv_fwd_mfma_kernel(const bf16* __res
     }
     return b;
   };
+  // the accumulators start at the bias of the lane's output channel (the
+  // fused inference starts there too)
+  const int o = lane % 32;
+  const float bo = bias[o];
   mfma_f32x16 acc;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int r = 0; r < 16; ++r) acc[r] = bo;
   if (CI == 4) {
 #pragma unroll
     for (int s = 0; s < 5; ++s) {  // K values 8s .. 8s+7 = taps 2s and 2s+1
@@ -271,13 +276,11 @@ __global__ __launch_bounds__(kBlock) void conv_fwd_mfma_kernel(const bf16* __res
       }
     }
   }
-  const int o = lane % 32;
-  const float bo = bias[o];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const long p = p0 + 8 * (r / 4) + 4 * kg + (r % 4);
     if (p < P) {
-      const float v = acc[r] + bo;
+      const float v = acc[r];
       store(y[p * CO + o], RELU ? fmaxf(v, 0.f) : v);
     }
   }
@@ -628,6 +631,15 @@ __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
   const f32x2_t f = {lo, hi};
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
+// ReLU of two packed bf16 values in one packed 16-bit integer max against 0:
+// a negative bf16 (-0 included) is a negative 16-bit integer.  Rounding
+// first and then clamping gives the same bits as clamping first for every
+// number (a NaN stays NaN).
+typedef short s16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w) {
+  const s16x2_t z = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2_t, w), z));
+}
 
 __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const* __restrict__ fields,
                                                              const float* __restrict__ prm,
@@ -692,6 +704,8 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
 
   const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
   const int ntiles = B * tiles_x * tiles_y;
+  // input scales as reciprocals (as features_kernel)
+  const float i0 = 1.f / s0, i1 = 1.f / s1, i2 = 1.f / s2, i3 = 1.f / s3;
 
   auto mfma32 = [&](uint4 a, uint2 b_lo, uint2 b_hi, mfma_f32x16 acc) {
     const mfma_u32x4 bv = {b_lo.x, b_lo.y, b_hi.x, b_hi.y};
@@ -704,17 +718,28 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
                                                     __builtin_bit_cast(mfma_bf16x8, bv), acc, 0, 0, 0);
   };
   const uint2 z2 = make_uint2(0u, 0u);
-  // the lane's result (16 rows = output channels 8 j + 4 kg + i of one
-  // pixel) with bias and ReLU, zero for pixels outside the image rows, as
-  // four packed 8-byte words; layer: 0 or 1
-  auto store_rows = [&](uint16_t* dst, const mfma_f32x16& acc, int layer, bool inside) {
+  // accumulators of layer 1 or 2 start at the layer's bias: row 8 j + 4 kg
+  // + i of the lane's 32 x 32 result is output channel 8 j + 4 kg + i
+  auto bias_init = [&](mfma_f32x16& acc, int layer) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float4 bj = bls[8 * layer + 2 * j + kg];
+      acc[4 * j + 0] = bj.x;
+      acc[4 * j + 1] = bj.y;
+      acc[4 * j + 2] = bj.z;
+      acc[4 * j + 3] = bj.w;
+    }
+  };
+  // the lane's result (16 rows = output channels 8 j + 4 kg + i of one
+  // pixel, bias included) after ReLU, zero for pixels outside the image
+  // rows, as four packed 8-byte words
+  auto store_rows = [&](uint16_t* dst, const mfma_f32x16& acc, bool inside) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
       uint2 v = z2;
       if (inside) {
-        v.x = bf16_pair(fmaxf(acc[4 * j + 0] + bj.x, 0.f), fmaxf(acc[4 * j + 1] + bj.y, 0.f));
-        v.y = bf16_pair(fmaxf(acc[4 * j + 2] + bj.z, 0.f), fmaxf(acc[4 * j + 3] + bj.w, 0.f));
+        v.x = relu_bf16x2(bf16_pair(acc[4 * j + 0], acc[4 * j + 1]));
+        v.y = relu_bf16x2(bf16_pair(acc[4 * j + 2], acc[4 * j + 3]));
       }
       *reinterpret_cast<uint2*>(dst + 8 * j + 4 * kg) = v;
     }
@@ -765,8 +790,8 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
             const float uc = 0.5f * (ld[it][0] + ld[it][1]);
             const float vn = (y + 1 < H) ? ld[it][3] : 0.f;
             const float vc = 0.5f * (ld[it][2] + vn);
-            pk.x = bf16_pair(uc / s0, vc / s1);
-            pk.y = bf16_pair(ld[it][4] / s2, ld[it][5] / s3);
+            pk.x = bf16_pair(uc * i0, vc * i1);
+            pk.y = bf16_pair(ld[it][4] * i2, ld[it][5] * i3);
           }
           *reinterpret_cast<uint2*>(&a2x[q * 4]) = pk;
         }
@@ -785,8 +810,8 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
         const int ry0 = v0 ? d0 / kR1W : 0, rx0 = v0 ? d0 % kR1W : 0;
         const int ry1 = v1 ? d1 / kR1W : 0, rx1 = v1 ? d1 % kR1W : 0;
         mfma_f32x16 acc0, acc1;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+        bias_init(acc0, 0);
+        bias_init(acc1, 0);
 #pragma unroll
         for (int st = 0; st < 3; ++st) {
           const int ta = 4 * st + 2 * kg, tb = ta + 1;
@@ -796,8 +821,8 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
           acc0 = mfma32(w1r[st], xin(ry0, rx0, ta), xin(ry0, rx0, tb), acc0);
           acc1 = mfma32(w1r[st], xin(ry1, rx1, ta), xin(ry1, rx1, tb), acc1);
         }
-        if (v0) store_rows(&a1[d0 * kAS], acc0, 0, d0 >= in_lo && d0 < in_hi);
-        if (v1) store_rows(&a1[d1 * kAS], acc1, 0, d1 >= in_lo && d1 < in_hi);
+        if (v0) store_rows(&a1[d0 * kAS], acc0, d0 >= in_lo && d0 < in_hi);
+        if (v1) store_rows(&a1[d1 * kAS], acc1, d1 >= in_lo && d1 < in_hi);
       }
     }
     __syncthreads();
@@ -817,9 +842,7 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
       }
       mfma_f32x16 acc[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+      for (int i = 0; i < 3; ++i) bias_init(acc[i], 1);
 #pragma unroll
       for (int st = 0; st < 18; ++st) {
         const int tap = st / 2, off = ((tap / 3) * kR1W + tap % 3) * kAS + 16 * (st % 2);
@@ -832,7 +855,7 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i)
-        if (dd[i] < kR2N) store_rows(&a2x[dd[i] * kAS], acc[i], 1, dd[i] >= in_lo && dd[i] < in_hi);
+        if (dd[i] < kR2N) store_rows(&a2x[dd[i] * kAS], acc[i], dd[i] >= in_lo && dd[i] < in_hi);
     }
     __syncthreads();
 
