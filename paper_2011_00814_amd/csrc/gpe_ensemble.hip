@@ -13,9 +13,11 @@
 // Tiles are TX columns x ZC rows (internal X x Z).  The table lists the
 // tiles case by case and is permuted so that the round-robin dispatch of
 // work-groups over the 8 XCDs gives each XCD a contiguous run of it: the
-// tiles of one case share halo rows in the same L2.
+// tiles of one case share halo rows in the same L2.  Within a run the
+// tallest tiles come first, so that a launch ends on short tiles.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -94,6 +96,27 @@ int check_batch(const gpe_params* c, int count) {
     if (gpe_workspace_bytes(&c[i]) == 0) return GPE_EINVAL;
   }
   return GPE_OK;
+}
+
+// Tallest tiles first within each XCD's run of a tile list (the runs that
+// xcd_order below hands to the XCDs): a stable sort by the tile's row count,
+// so the tiles of one case stay together.  The work-groups dispatched last on
+// an XCD are then the shortest, and a launch does not end with a few tall
+// tiles running on an otherwise idle XCD.
+void tallest_first(std::vector<int4>& list, const std::vector<int>& zc, const std::vector<int>& nz) {
+  const int nb = (int)list.size();
+  const int per = nb / 8, rem = nb % 8;
+  auto rows = [&](const int4& t) {
+    const int left = nz[t.x] - t.w * zc[t.x];
+    return left < zc[t.x] ? left : zc[t.x];
+  };
+  int o = 0;
+  for (int x = 0; x < 8; ++x) {
+    const int n = per + (x < rem ? 1 : 0);
+    std::stable_sort(list.begin() + o, list.begin() + o + n,
+                     [&](const int4& a, const int4& b) { return rows(a) > rows(b); });
+    o += n;
+  }
 }
 
 // XCD-contiguous order of a tile list (the host twin of tile_of_block):
@@ -181,10 +204,13 @@ int upload_tables(gpe_ensemble* e) {
   std::vector<int4> ft, ct;
   std::vector<const void*> fields(4 * (size_t)n, nullptr);
   std::vector<int64_t> ncell(n);
+  std::vector<int> zcs(n), nzs(n);
   for (int i = 0; i < n; ++i) {
     const gpe_state* s = e->cases[i];
     const int nx = s->grid.n[0], nz = s->grid.n[2];
     const int zc = clamp_rows(e->rows[i], nz);
+    zcs[i] = zc;
+    nzs[i] = nz;
     for (int st = 1; st <= 3; ++st) fa[(size_t)(st - 1) * n + i] = flow_args<T>(s, st, zc);
     ChArgs<T> h[4];
     int stage[4];
@@ -207,6 +233,8 @@ int upload_tables(gpe_ensemble* e) {
   if ((int)ft.size() > e->L.max_flow_tiles || (int)ct.size() > e->L.max_ch_tiles) return GPE_EINVAL;
   e->nflow_tiles = (int)ft.size();
   e->nch_tiles = (int)ct.size();
+  tallest_first(ft, zcs, nzs);
+  tallest_first(ct, zcs, nzs);
   ft = xcd_order(ft);
   ct = xcd_order(ct);
   char* w = e->ws;
