@@ -186,6 +186,31 @@ struct KernelTimer {
 // Longest Z chunk per work-group (planes): see choose_zchunk.
 int zchunk_max(size_t esize) { return esize == 8 ? 128 : 64; }
 
+// Rows per work-group of a 2-D grid.  A 2-D work-group is one wave on a
+// 64-column strip, and a single 2-D grid gives few of them: a launch then
+// lasts about as long as one work-group takes to stage its first rows and
+// march its own, each row waiting on the loads issued one row earlier, times
+// the rounds of work-groups the device needs.  The chunk minimises
+// rounds x (rows + 3 staged warm-up rows) over 1 .. zmax rows; smaller
+// chunks win ties.  On MI355X this halves the step of grids up to 256 x 256
+// against chunks of 8 rows or more, and it picks the measured best chunk on
+// 64^2, 256^2, 96 x 32 and 256 x 1024.
+int rows_2d(const int n[3], int tx, int bpc, int ncu, int zmax) {
+  const long tiles = (n[0] + tx - 1) / tx;
+  const long slots = (long)ncu * bpc;
+  int best = 1;
+  long best_t = -1;
+  for (int zc = 1; zc <= std::min(n[2], zmax); ++zc) {
+    const long w = tiles * ((n[2] + zc - 1) / zc);
+    const long t = (w + slots - 1) / slots * (zc + 3);
+    if (best_t < 0 || t < best_t) {
+      best_t = t;
+      best = zc;
+    }
+  }
+  return best;
+}
+
 int flow_zchunk(const gpe_state* s, size_t esize) {
   if (s->P.zchunk > 0) return std::min(s->P.zchunk, s->grid.n[2]);
   const int zmax = zchunk_max(esize);
@@ -194,8 +219,7 @@ int flow_zchunk(const gpe_state* s, size_t esize) {
                                            gpe::FlowTile<3, double>::BPC, s->ncu, zmax)
                       : gpe::choose_zchunk(s->grid.n, gpe::FlowTile<3, float>::TX, gpe::FlowTile<3, float>::TY,
                                            gpe::FlowTile<3, float>::BPC, s->ncu, zmax);
-  return gpe::choose_zchunk(s->grid.n, gpe::FlowTile<2, float>::TX, gpe::FlowTile<2, float>::TY,
-                            gpe::FlowTile<2, float>::BPC, s->ncu, zmax);
+  return rows_2d(s->grid.n, gpe::FlowTile<2, float>::TX, gpe::FlowTile<2, float>::BPC, s->ncu, zmax);
 }
 
 int ch_zchunk(const gpe_state* s, size_t esize) {
@@ -206,8 +230,7 @@ int ch_zchunk(const gpe_state* s, size_t esize) {
                                            gpe::ChTile<3, double>::BPC, s->ncu, zmax)
                       : gpe::choose_zchunk(s->grid.n, gpe::ChTile<3, float>::TX, gpe::ChTile<3, float>::TY,
                                            gpe::ChTile<3, float>::BPC, s->ncu, zmax);
-  return gpe::choose_zchunk(s->grid.n, gpe::ChTile<2, float>::TX, gpe::ChTile<2, float>::TY,
-                            gpe::ChTile<2, float>::BPC, s->ncu, zmax);
+  return rows_2d(s->grid.n, gpe::ChTile<2, float>::TX, gpe::ChTile<2, float>::BPC, s->ncu, zmax);
 }
 
 template <typename T>
