@@ -367,7 +367,7 @@ int gpe_ensemble_create(const gpe_params* cases, int32_t count, void* d_workspac
 int gpe_ensemble_run_n(gpe_ensemble* e, int64_t nsteps);
 
 /* Tile autotuner: for every group of cases with the same number of rows,
- * try work-group tile heights of 4, 8, 16, 32, 64 and 128 rows (clamped to the
+ * try work-group tile heights of 1, 2, 4, 8, 16, 32, 64 and 128 rows (clamped to the
  * grid) and keep the one with the shortest batch step, timed over
  * trial_steps graph-replayed steps per candidate (one size group at a time,
  * the others held fixed).  The trial steps are real steps: every case

@@ -34,8 +34,8 @@ using namespace gpe_host;
 
 constexpr int kMaxCases = 65535;
 constexpr int kEnsZChunk = 32;   // default rows per work-group tile of a case
-constexpr int kMinZChunk = 4;    // smallest tile height (sizes the tile tables)
-constexpr int kTuneRows[] = {4, 8, 16, 32, 64, 128};  // candidates of the autotuner
+constexpr int kMinZChunk = 1;    // smallest tile height (sizes the tile tables)
+constexpr int kTuneRows[] = {1, 2, 4, 8, 16, 32, 64, 128};  // candidates of the autotuner
 constexpr int kFinBlocks = 8;    // work-groups per case of the finite check
 
 int clamp_rows(int rows, int nz) { return rows < nz ? rows : nz; }

@@ -66,7 +66,7 @@ def test_autotuned_tiles_keep_results_bitwise(gpe):
     ens.run(5)
     ens.synchronize()
     _say(f"[ensemble] autotuned rows {list(rows)}")
-    assert all(r in (4, 8, 16, 32, 64, 128) or r == c["n"][1] for r, c in zip(rows, cases))
+    assert all(r in (1, 2, 4, 8, 16, 32, 64, 128) or r == c["n"][1] for r, c in zip(rows, cases))
     for i, prob in enumerate(cases):
         a = ens.case(i)
         nsteps = a.diagnostics()["step"]
