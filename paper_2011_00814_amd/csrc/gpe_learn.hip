@@ -621,12 +621,11 @@ constexpr int kN1 = (kR1N + 31) / 32, kN2 = (kR2N + 31) / 32;  // 32-pixel colum
 
 typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
 
-// round to nearest even in one instruction (v_cvt_pk_bf16_f32); equal to
-// store(bf16&, float) except for the payload of a NaN
-__device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
-// two values rounded and packed by one v_cvt_pk_bf16_f32 (lo in the low half)
+// two values rounded to nearest even and packed by one v_cvt_pk_bf16_f32 (lo
+// in the low half); equal to two store(bf16&, float) except for the payload
+// of a NaN
 __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
   const f32x2_t f = {lo, hi};
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
