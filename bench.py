@@ -26,6 +26,12 @@ four-node CPU figure, context only).
 `--workload ensemble` measures the ensemble alone (default 5000 steps):
 aggregate cell updates per second of the batch against the same cases run
 one after another as plain single grids.
+
+`--workload rt2d` times the 2-D Rayleigh-Taylor grid (256 x 1024, walls in
+y, FP32 and FP64 unless --precision is given; default 2000 steps) as graph-
+replayed steps; the value is the FP32 (or the given precision's) MLUPS.
+The grid's fields fit in the device's last-level cache, so no HBM roofline
+is given for it.
 """
 from __future__ import annotations
 
@@ -430,7 +436,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-configs", action="store_true",
                     help="also time the CPU oracle on every configuration, all cores and one core (about 2 min)")
-    ap.add_argument("--workload", choices=("bubble3d", "ensemble", "learned", "coalescence"), default="bubble3d")
+    ap.add_argument("--workload", choices=("bubble3d", "ensemble", "learned", "coalescence", "rt2d"),
+                    default="bubble3d")
     ap.add_argument("--learned-summary", type=int, default=1,
                     help="include a reduced learned-correction run in the default line (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
@@ -529,6 +536,28 @@ def main():
             "vs_baseline": row["ratio_vs_paper"],
             "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
             "config": {"workload": r["workload"] + ", D3Q15"}, "coalescence": r}), flush=True)
+        return
+    if args.workload == "rt2d":
+        from paper_2011_00814_amd import workloads as W
+
+        precs = (args.precision,) if "--precision" in sys.argv else ("fp32", "fp64")
+        steps = args.steps if "--steps" in sys.argv else 2000
+        rows = []
+        for prec in precs:
+            prob, _ = W.rayleigh_taylor_2d(precision=prec, in_kernel_init=True)
+            r = time_solver(prob, steps, args.warmup)
+            rows.append({"precision": prec, "mlups": round(r["ncell"] / (r["graph_ms_per_step"] * 1e-3) / 1e6, 1),
+                         "graph_ms_per_step": round(r["graph_ms_per_step"], 5),
+                         "eager_ms_per_step": round(r["ms_per_step"], 5),
+                         "kernels_us": {k[0]: round(k[1] * 1000, 1) for k in r["ktimes"]},
+                         "finite": r["diag"]["finite"], "mass_drift": r["diag"]["mass_drift"]})
+        print(json.dumps({
+            "metric": "MLUPS of the full RK3 step, 2-D Rayleigh-Taylor 256x1024 (graph-replayed steps)",
+            "value": rows[0]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": rows[0]["graph_ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32" if precs[0] == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": "2-D Rayleigh-Taylor 256x1024, periodic x, no-slip walls in y, Atwood 0.5, "
+                                   "Re 3000, D2Q9, RK3 flow + RK2 CH"}, "rt2d": rows}), flush=True)
         return
     if args.workload == "ensemble":
         steps = args.steps if "--steps" in sys.argv else 5000

@@ -117,12 +117,13 @@ def static_drop_2d(n=64, R=16.0, W=2.0, precision="fp64"):
     return prob, st
 
 
-def rayleigh_taylor_2d(nx=256, ny=1024, precision="fp64", amp_frac=0.1, W=2.0):
+def rayleigh_taylor_2d(nx=256, ny=1024, precision="fp64", amp_frac=0.1, W=2.0, in_kernel_init=False):
     """2-D Rayleigh-Taylor: x periodic, no-slip walls at y = 0 and y = ny;
     Atwood 0.5 (rho_G = 1/3), viscosity ratio 1, Re = 3000 on lambda = nx with
     U_c = sqrt(g lambda) = 0.05, sigma = 0, Pe = 8e4 (M = U_c lambda^2 / Pe),
     rho_ref = rho_G; heavy fluid (phi = +1) on top of the cosine-perturbed
-    interface y0 = ny/2 + amp_frac*nx*cos(2 pi x / nx)."""
+    interface y0 = ny/2 + amp_frac*nx*cos(2 pi x / nx) (the in-kernel layer
+    profile, init kind 3, with in_kernel_init; then no state is built)."""
     lam = float(nx)
     Uc = 0.05
     g = Uc * Uc / lam
@@ -132,6 +133,9 @@ def rayleigh_taylor_2d(nx=256, ny=1024, precision="fp64", amp_frac=0.1, W=2.0):
         rho_l=1.0, rho_g=1.0 / 3.0, eta_l=eta, eta_g=eta, sigma=0.0,
         mob=Uc * lam * lam / 8e4, width=W, g=(0.0, -g, 0.0), rho_ref=1.0 / 3.0,
         precision=precision)
+    if in_kernel_init:
+        prob["init"] = {"kind": 3, "center": (0.0, ny / 2, 0.0), "amp": amp_frac * nx, "width": W}
+        return prob, None
     x, y, _ = _centres(prob)
     y0 = ny / 2 + amp_frac * nx * np.cos(2 * math.pi * x / nx)
     st = zero_state(prob)

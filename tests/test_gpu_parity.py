@@ -387,6 +387,19 @@ def test_unstable_rejected(gpe):
     assert e.value.code == gpe.GPE_EUNSTABLE
 
 
+def test_layer_init_matches_host_profile(gpe):
+    """The in-kernel layer profile (init kind 3) that the Rayleigh-Taylor
+    benchmark starts from equals the host-built profile of the same set-up."""
+    for prec, tol in (("fp64", 1e-14), ("fp32", 1e-6)):
+        prob, st = W.rayleigh_taylor_2d(nx=70, ny=96, precision=prec)
+        probk, none = W.rayleigh_taylor_2d(nx=70, ny=96, precision=prec, in_kernel_init=True)
+        assert none is None
+        s = gpe.Solver(probk, None)
+        phi = s.get("phi")
+        s.close()
+        assert np.max(np.abs(phi - st["phi"])) < tol, prec
+
+
 def test_rest_state_bitwise_gpu(gpe):
     for dim, bc in ((2, (1, 1, 2, 2, 0, 0)), (3, (1, 1, 0, 0, 2, 2))):
         n = (70, 37, 1) if dim == 2 else (40, 19, 40)
