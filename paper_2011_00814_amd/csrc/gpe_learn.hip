@@ -908,14 +908,23 @@ __global__ __launch_bounds__(kBlock, 2) void cnn_infer_kernel(const float* const
   }
 }
 
-// per-case sums of the phi output from the per-tile sums, in tile order
-__global__ __launch_bounds__(kBlock) void case_sums_kernel(const float* partial, int B, int tiles_per_case,
-                                                           float* sums) {
-  const int b = (int)(blockIdx.x * kBlock + threadIdx.x);
-  if (b >= B) return;
+// per-case sums of the phi output from the per-tile sums, in tile order: the
+// block of case b loads kBlock of its partials into LDS at a time (one memory
+// latency per chunk instead of one per tile), then one lane adds them in order
+__global__ __launch_bounds__(kBlock) void case_sums_kernel(const float* partial, int tiles_per_case, float* sums) {
+  __shared__ float part[kBlock];
+  const int b = (int)blockIdx.x;
+  const float* src = partial + (size_t)b * tiles_per_case;
   float s = 0.f;
-  for (int t = 0; t < tiles_per_case; ++t) s += partial[(size_t)b * tiles_per_case + t];
-  sums[b] = s;
+  for (int t0 = 0; t0 < tiles_per_case; t0 += kBlock) {
+    const int n = tiles_per_case - t0 < kBlock ? tiles_per_case - t0 : kBlock;
+    if ((int)threadIdx.x < n) part[threadIdx.x] = src[t0 + (int)threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int t = 0; t < n; ++t) s += part[t];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[b] = s;
 }
 
 // ---- launch helpers ----------------------------------------------------------------
@@ -1030,7 +1039,7 @@ int infer_launch(float* const* d_fields, const float* d_params, const void* d_pa
                      (const bf16*)d_params_bf16, B, H, W, in_scale[0], in_scale[1], in_scale[2], in_scale[3], d_out,
                      partial);
   float* sums = partial + ntiles;
-  hipLaunchKernelGGL(case_sums_kernel, dim3(blocks_for(B)), dim3(kBlock), 0, s, (const float*)partial, B, tpc, sums);
+  hipLaunchKernelGGL(case_sums_kernel, dim3((unsigned)B), dim3(kBlock), 0, s, (const float*)partial, tpc, sums);
   hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
                      out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)sums);
   return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
