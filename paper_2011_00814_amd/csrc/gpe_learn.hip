@@ -568,6 +568,46 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(float* const* fields, con
   fields[4 * b + 3][o] += s3 * (d[3] - mean);
 }
 
+// apply_kernel with the case means taken from the per-tile sums of the phi
+// output (tiles_per_case consecutive entries per case, in tile order) instead
+// of per-case sums: a block's pixels lie in at most two cases (H W >= kBlock),
+// whose tile sums (<= kBlock / 2 each) it loads into LDS together and adds in
+// order in one lane per case, the same additions in the same order as
+// case_sums_kernel, so the correction has the same bits and needs no launch
+// of its own.
+__global__ __launch_bounds__(kBlock) void apply_tiles_kernel(float* const* fields, const float* out, int B, int H,
+                                                             int W, float s0, float s1, float s2, float s3,
+                                                             const float* partial, int tiles_per_case) {
+  __shared__ float part[kBlock];
+  __shared__ float csum[2];
+  const long n = (long)B * H * W, hw = (long)H * W;
+  const long q0 = (long)blockIdx.x * kBlock;
+  const int b0 = (int)(q0 / hw);
+  const int nb = (int)(((q0 + kBlock < n ? q0 + kBlock : n) - 1) / hw) - b0 + 1;  // 1 or 2
+  const int t = (int)threadIdx.x;
+  if (t < nb * tiles_per_case) part[t] = partial[(size_t)b0 * tiles_per_case + t];
+  __syncthreads();
+  if (t < nb) {
+    float sum = 0.f;
+    for (int i = 0; i < tiles_per_case; ++i) sum += part[t * tiles_per_case + i];
+    csum[t] = sum;
+  }
+  __syncthreads();
+  const long q = q0 + t;
+  if (q >= n) return;
+  const int x = (int)(q % W);
+  const long r = q / W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  const size_t o = (size_t)y * W + x;
+  const float* d = out + q * 4;
+  const float mean = csum[b - b0] / (float)(H * W);
+  fields[4 * b + 0][o] += s0 * d[0];
+  if (y > 0) fields[4 * b + 1][o] += s1 * d[1];  // the wall face of row 0 stays 0
+  fields[4 * b + 2][o] += s2 * d[2];
+  fields[4 * b + 3][o] += s3 * (d[3] - mean);
+}
+
 // ---- interface position -----------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void interface_kernel(const float* const* phi, int B, int H, int W,
                                                            float* out) {
@@ -1038,10 +1078,15 @@ int infer_launch(float* const* d_fields, const float* d_params, const void* d_pa
   hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(kBlock), 0, s, d_fields, d_params,
                      (const bf16*)d_params_bf16, B, H, W, in_scale[0], in_scale[1], in_scale[2], in_scale[3], d_out,
                      partial);
-  float* sums = partial + ntiles;
-  hipLaunchKernelGGL(case_sums_kernel, dim3((unsigned)B), dim3(kBlock), 0, s, (const float*)partial, tpc, sums);
-  hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
-                     out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)sums);
+  if ((long)H * W >= kBlock && tpc <= kBlock / 2) {
+    hipLaunchKernelGGL(apply_tiles_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B,
+                       H, W, out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)partial, tpc);
+  } else {
+    float* sums = partial + ntiles;
+    hipLaunchKernelGGL(case_sums_kernel, dim3((unsigned)B), dim3(kBlock), 0, s, (const float*)partial, tpc, sums);
+    hipLaunchKernelGGL(apply_kernel, dim3(blocks_for((long)B * H * W)), dim3(kBlock), 0, s, d_fields, d_out, B, H, W,
+                       out_scale[0], out_scale[1], out_scale[2], out_scale[3], (const float*)sums);
+  }
   return hipGetLastError() == hipSuccess ? GPE_OK : GPE_EHIP;
 }
 
