@@ -110,15 +110,16 @@ size_t gpe_cnn_infer_scratch_bytes(int32_t B, int32_t H, int32_t W);
 /* Fused inference with BF16 operands: the network input of B coarse states,
  * the three convolutions (all on the matrix cores, FP32 accumulation) and
  * the correction of the states, the same operations as gpe_cnn_features,
- * gpe_cnn_forward and gpe_cnn_apply with GPE_ACT_BF16, in three launches and
- * without storing activations in device memory (a work-group keeps a 32 x 8
+ * gpe_cnn_forward and gpe_cnn_apply with GPE_ACT_BF16, in two launches (three
+ * when H W < 256 or a state has more than 128 tiles) and without storing
+ * activations in device memory (a work-group keeps a 32 x 8
  * tile's activations, with their halos, in LDS).  d_params are the FP32
  * master parameters (biases), d_params_bf16 their GPE_ACT_BF16 copy
  * (gpe_cnn_convert); d_out receives the network output [B][H][W][4] as
  * gpe_cnn_forward writes it.  Every layer uses the double-K MFMA and adds
  * in another order than the unfused kernels (and rounds NaN payloads
- * differently), so results agree with them to FP32 rounding, not bitwise.  d_scratch: gpe_cnn_infer_scratch_bytes(B, H, W)
- * bytes. */
+ * differently), so results agree with them to FP32 rounding, not bitwise.
+ * d_scratch: gpe_cnn_infer_scratch_bytes(B, H, W) bytes. */
 int gpe_cnn_infer(float* const* d_fields, const float* d_params, const void* d_params_bf16, int32_t B, int32_t H,
                   int32_t W, const float in_scale[4], const float out_scale[4], float* d_out, void* d_scratch,
                   size_t scratch_bytes, void* stream);
